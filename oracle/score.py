@@ -15,10 +15,13 @@ E_inter (direct mode): sum over receptor atoms inside the cutoffs, the
   paper's own pairwise form; used by invariance tests.
 E_intra: sum over the intra-ligand pair list of sum_k w_k phi_k(r_ij).
 
-Margins: the smallest distance (A) from any decision threshold the result
-depends on (cell faces, box faces, pair cutoffs, kinks of the piecewise
-terms); two implementations that compute positions in different precisions
-can legitimately disagree only when a margin is below their position error.
+Margins: `margin` is the smallest distance (A) from any decision threshold
+the result depends on (cell faces, box faces, pair cutoffs, kinks of the
+piecewise terms); `margin_E` only counts thresholds where the energy itself
+jumps (hard pair cutoffs).  Two implementations that compute positions in
+different precisions can legitimately disagree in the gradient only when
+`margin` is below their position error, and in the energy only when
+`margin_E` is.
 """
 from dataclasses import dataclass
 import numpy as np
@@ -91,6 +94,14 @@ def trilerp(M, grid, p):
     return v, g, eout, gout, margin, (c, f)
 
 
+def cells(grid, p):
+    """Cell index [n,3] (x, y, z) of each point, as trilerp chooses it."""
+    p = np.asarray(p, np.float64)
+    n = np.asarray(grid.dims)
+    pc = np.clip(p, grid.lo, grid.hi)
+    return np.clip(np.floor((pc - grid.lo) / grid.spacing).astype(np.int64), 0, n - 2)
+
+
 def corner_weights(f):
     """Trilinear weights of the 8 cell corners, ordered (dx, dy, dz) loops."""
     fx, fy, fz = f[:, 0], f[:, 1], f[:, 2]
@@ -101,6 +112,15 @@ def corner_weights(f):
                 out.append((dx, dy, dz, (fx if dx else 1 - fx) * (fy if dy else 1 - fy)
                             * (fz if dz else 1 - fz)))
     return out
+
+
+def _jumps(preset, ti, tj):
+    """Distances where a term of this type pair jumps in value (hard cutoffs
+    of terms that are nonzero there; the clash cutoff is continuous)."""
+    cuts = P.term_cutoffs(preset, ti, tj)
+    if preset == P.PRESET_TRIDS:
+        return [c for k, c in enumerate(cuts) if c is not None and k != 1]
+    return [P.VINA_CUTOFF]
 
 
 def _breakpoints(preset, ti, tj):
@@ -118,13 +138,15 @@ def _breakpoints(preset, ti, tj):
 
 
 def intra(topo, preset, weights, x):
-    """E_intra [P], gradient [P,N,3], per-pair |energy| sum [P], margin [P]."""
+    """E_intra [P], gradient [P,N,3], per-pair |energy| sum [P], margin [P],
+    value-jump margin [P]."""
     x = np.asarray(x, np.float64)
     Pn = x.shape[0]
     E = np.zeros(Pn)
     g = np.zeros_like(x)
     sabs = np.zeros(Pn)
     margin = np.full(Pn, np.inf)
+    margin_e = np.full(Pn, np.inf)
     w = np.asarray(weights, np.float64)
     for i, j in topo.pairs:
         ti, tj = int(topo.types[i]), int(topo.types[j])
@@ -141,7 +163,9 @@ def intra(topo, preset, weights, x):
         g[:, j] -= fij
         for b in _breakpoints(preset, ti, tj):
             margin = np.minimum(margin, np.abs(d - b))
-    return E, g, sabs, margin
+        for b in _jumps(preset, ti, tj):
+            margin_e = np.minimum(margin_e, np.abs(d - b))
+    return E, g, sabs, margin, margin_e
 
 
 class Scorer:
@@ -171,19 +195,67 @@ class Scorer:
         q = np.atleast_2d(np.asarray(q, np.float64))
         x = FK.fk(topo, q)
         e, g, eo, go, mg = self.inter(topo.types, x)
-        Ei, gi, sabs_i, mi = intra(topo, self.preset, self.weights, x)
+        Ei, gi, sabs_i, mi, mie = intra(topo, self.preset, self.weights, x)
         E = e.sum(1) + eo.sum(1) + Ei
         gat = g + go + gi
         dq = FK.dof_gradient(topo, q, x, gat)
         out = dict(E=E, dEdq=dq, x=x, g=gat,
                    S_abs=np.abs(e).sum(1) + eo.sum(1) + sabs_i,
-                   margin=np.minimum(mg.min(1) if mg.size else np.inf, mi))
+                   margin=np.minimum(mg.min(1) if mg.size else np.inf, mi), margin_E=mie)
         if want_parts:
             out.update(E_inter=e.sum(1), E_out=eo.sum(1), E_intra=Ei)
         return out
 
     def energy(self, topo, q):
         return self.score(topo, q)["E"]
+
+
+class _LazyMap:
+    """Combined maps filled on demand: a node's value is computed (by the
+    brute-force pair sum of maps.node_values) the first time it is read."""
+
+    def __init__(self, pocket, preset, weights):
+        self.pocket = pocket
+        self.preset = preset
+        self.w = np.asarray(weights, np.float64)
+        nx, ny, nz = pocket.dims
+        self.M = np.zeros((8, nz, ny, nx))
+        self.done = np.zeros((nz, ny, nx), bool)
+
+    def ensure(self, iz, iy, ix):
+        nx, ny, nz = self.pocket.dims
+        flat = np.unique((np.asarray(iz) * ny + np.asarray(iy)) * nx + np.asarray(ix))
+        flat = flat[~self.done.reshape(-1)[flat]]
+        if len(flat) == 0:
+            return
+        pts = MAPS.node_coords(self.pocket.origin, self.pocket.spacing, self.pocket.dims, flat)
+        G = MAPS.node_values(self.pocket.xyz, self.pocket.type, pts, self.preset)   # [8, K, n]
+        vals = np.einsum("k,tkn->tn", self.w, G)
+        z, rem = np.divmod(flat, nx * ny)
+        y, x = np.divmod(rem, nx)
+        self.M[:, z, y, x] = vals
+        self.done[z, y, x] = True
+
+
+class LazyScorer(Scorer):
+    """Grid-mode scorer whose map nodes are computed only where poses need them."""
+
+    def __init__(self, pocket, preset=P.PRESET_TRIDS, weights=None):
+        self.preset = preset
+        self.weights = np.asarray(P.default_weights(preset) if weights is None else weights,
+                                  np.float64)
+        self.grid = grid_of(pocket)
+        self.pocket = pocket
+        self.lazy = _LazyMap(pocket, preset, self.weights)
+        self.M = self.lazy.M
+
+    def inter(self, types, x):
+        c = cells(self.grid, x.reshape(-1, 3))
+        for dz in (0, 1):
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    self.lazy.ensure(c[:, 2] + dz, c[:, 1] + dy, c[:, 0] + dx)
+        return Scorer.inter(self, types, x)
 
 
 class DirectScorer:
@@ -223,6 +295,6 @@ class DirectScorer:
         q = np.atleast_2d(np.asarray(q, np.float64))
         x = FK.fk(topo, q)
         e, g = self.inter_atoms(topo.types, x)
-        Ei, gi, _, _ = intra(topo, self.preset, self.weights, x)
+        Ei, gi, _, _, _ = intra(topo, self.preset, self.weights, x)
         gat = g + gi
         return dict(E=e.sum(1) + Ei, dEdq=FK.dof_gradient(topo, q, x, gat), x=x, g=gat)
