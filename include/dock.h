@@ -1,0 +1,260 @@
+/*
+ * dock.h -- C ABI of the MI355X docking hot path (libdock.so).
+ *
+ * The library evaluates the TRIDS physics scoring function (arXiv
+ * 2510.24186, Methods, "Scoring functions": E_long, E_clash, E_Hbond and
+ * their weighted sum E_dock, without the learned MDN term) and its gradient
+ * with respect to each pose's translation, rotation and torsion DOFs
+ * (Methods, "Conformation sampling"), and drives many independent Metropolis
+ * Monte Carlo + local-gradient trajectories per ligand (Fig. 2).  Receptor
+ * terms are tabulated on per-ligand-type grid maps; ligand-internal pairs are
+ * summed directly.
+ *
+ * Conventions shared by every call
+ *  - Every call returns DOCK_OK (0) or a negative dock_status.  On error no
+ *    output buffer is modified and dock_last_error() (thread-local) holds a
+ *    message.  No C++ exception crosses the ABI.
+ *  - "host" pointers are read during the call and copied; "device" pointers
+ *    are HIP device memory owned by the caller (e.g. torch tensor storage).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *    enqueued asynchronously on it unless stated otherwise.
+ *  - Handles are immutable after creation (runs excepted), so concurrent
+ *    read-only calls on different streams are safe.
+ *  - Poses: q = (Tx, Ty, Tz, alpha, beta, gamma, theta_0 .. theta_{n_t-1}),
+ *    row-major with a caller-chosen row stride q_stride >= 6 + n_t.  T is
+ *    where the root fragment's centroid lands; R = Rz(alpha) Ry(beta)
+ *    Rx(gamma) turns about it; theta_k are torsion deltas from the input
+ *    pose.  Angles are radians; energies are in the score's units.
+ */
+#ifndef DOCK_H
+#define DOCK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DOCK_ABI_VERSION 1
+#define DOCK_MAX_ATOMS 128
+#define DOCK_MAX_TORS 32
+#define DOCK_N_TYPES 8
+#define DOCK_MAX_TERMS 5
+
+typedef enum {
+  DOCK_OK = 0,
+  DOCK_E_ARG = -1,      /* invalid argument, size or handle */
+  DOCK_E_TOPOLOGY = -2, /* disconnected ligand, rotatable ring bond, bad bond */
+  DOCK_E_LIMIT = -3,    /* N > DOCK_MAX_ATOMS, n_t > DOCK_MAX_TORS, LDS budget */
+  DOCK_E_OOM = -4,      /* device or host allocation failed */
+  DOCK_E_HIP = -5       /* a HIP runtime call failed */
+} dock_status;
+
+enum { DOCK_PRESET_TRIDS = 0, DOCK_PRESET_VINA = 1 };
+enum { DOCK_LOCAL_ADAM = 0, DOCK_LOCAL_LINESEARCH = 1 };
+enum { DOCK_FORM_PLAIN = 0, DOCK_FORM_BATCHED = 1 };
+
+typedef struct dock_pocket_s* dock_pocket_t;
+typedef struct dock_ligands_s* dock_ligands_t;
+typedef struct dock_run_s* dock_run_t;
+
+/* ------------------------------------------------------------------------
+ * Pocket: receptor atoms -> grid maps (Methods, E_long / E_clash / E_Hbond;
+ * Discussion item 4: only pairs inside a cutoff are summed).
+ *
+ * G[t][k][node] = sum over receptor atoms i inside term k's cutoff of
+ * phi_k(|node - r_i|; t, type_i); the combined map M[t] = sum_k w_k G[t][k].
+ * Node (ix, iy, iz) sits at origin + spacing * (ix, iy, iz); layout
+ * [t][k][iz][iy][ix] (x fastest).  The inside-cutoff test uses the FP32
+ * squared distance ((dx*dx + dy*dy) + dz*dz) against fl32(c)^2, evaluated
+ * without contraction; the terms and their sums are evaluated in FP64 and
+ * stored as FP32.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_atoms;        /* receptor atoms, >= 0 */
+  const float* xyz;       /* host [n_atoms * 3] */
+  const uint8_t* type;    /* host [n_atoms], 0..7 (C_H C_P N_P N_D N_A O_A O_DA Cl_H) */
+  float origin[3];        /* first node */
+  float spacing;          /* > 0, Angstrom */
+  int32_t dims[3];        /* nx, ny, nz, each in [2, 1024] */
+  int32_t preset;         /* DOCK_PRESET_TRIDS (K = 3) or DOCK_PRESET_VINA (K = 5) */
+  const float* weights;   /* host [K] or NULL for the preset's weights
+                             (TRIDS 0.2 / 10 / 0.6, Methods E_dock) */
+  int32_t keep_per_term;  /* nonzero: also keep G (needed by the adjoint) */
+} dock_pocket_desc;
+
+/* Builds the maps on `stream`; the returned handle owns them.  The call
+ * returns after enqueueing; the maps are ready when the stream reaches it. */
+int dock_load_pocket(const dock_pocket_desc* desc, void* stream, dock_pocket_t* out);
+
+/* Device pointer to the combined maps M [8][nz][ny][nx] (per_term = 0) or to
+ * G [8][K][nz][ny][nx] (per_term = 1, only if kept).  Owned by the handle. */
+int dock_pocket_maps(dock_pocket_t p, int32_t per_term, float** dev_ptr, int64_t* n_floats);
+/* Copies the maps of dock_pocket_maps into `dst` (device, n_floats) on `stream`. */
+int dock_pocket_copy_maps(dock_pocket_t p, int32_t per_term, float* dst, void* stream);
+int dock_pocket_terms(dock_pocket_t p, int32_t* preset, int32_t* n_terms, float* weights /* host [K] */);
+int dock_free_pocket(dock_pocket_t p);
+
+/* ------------------------------------------------------------------------
+ * Ligands: typing, torsion tree and intra-ligand pair list, on the host.
+ *
+ * Typing: C -> C_P if bonded to N/O else C_H; N -> N_D if it carries H, else
+ * N_A if <= 2 heavy neighbours, else N_P; O -> O_DA if it carries H else O_A;
+ * Cl -> Cl_H.  Fragments: components after removing rotatable bonds (ids by
+ * lowest atom).  Root: the fragment of smallest tree height (lowest id on
+ * ties); torsion k = k-th non-root fragment in breadth-first order (children
+ * by id), axis a_k (parent side) -> b_k.  Pairs: atoms in different
+ * fragments >= 4 bonds apart.  Box: bounds of the input pose unless given.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_ligands;           /* >= 1 */
+  const int32_t* atom_off;     /* host [n_ligands + 1] */
+  const uint8_t* element;      /* host [total atoms]: 0 C, 1 N, 2 O, 3 Cl */
+  const uint8_t* n_h;          /* host [total atoms], implicit hydrogens */
+  const float* xyz;            /* host [total atoms * 3], input pose */
+  const int32_t* bond_off;     /* host [n_ligands + 1] */
+  const int32_t* bonds;        /* host [total bonds * 2], ligand-local indices */
+  const uint8_t* rotatable;    /* host [total bonds] */
+  const float* box_min;        /* host [n_ligands * 3] or NULL */
+  const float* box_max;        /* host [n_ligands * 3] or NULL */
+  const int32_t* pocket_index; /* host [n_ligands] or NULL (all 0) */
+  int32_t host_only;           /* nonzero: build topology only, no device upload
+                                  (such a handle serves dock_ligand_* queries) */
+} dock_ligand_desc;
+
+int dock_load_ligands(const dock_ligand_desc* desc, void* stream, dock_ligands_t* out);
+
+typedef struct {
+  int32_t n_atoms, n_tors, n_frags, n_pairs, root, height, pocket;
+  float c0[3];                 /* root-fragment centroid (FP64 mean, stored FP32) */
+  float box_min[3], box_max[3];
+} dock_ligand_info_t;
+
+int dock_ligand_info(dock_ligands_t L, int32_t lig, dock_ligand_info_t* info);
+/* Integer topology in the caller's atom numbering (host outputs, nullable):
+ * type [N], atom_frag [N], frag_parent [F] (-1 root), tors_frag [n_t],
+ * tors_atoms [n_t * 2] (a_k, b_k), pairs [n_pairs * 2], bfs [F]. */
+int dock_ligand_topology(dock_ligands_t L, int32_t lig, uint8_t* type, int32_t* atom_frag,
+                         int32_t* frag_parent, int32_t* tors_frag, int32_t* tors_atoms,
+                         int32_t* pairs, int32_t* bfs);
+int dock_ligands_count(dock_ligands_t L, int32_t* n_ligands, int32_t* max_atoms,
+                       int32_t* max_tors, int64_t* total_atoms);
+int dock_free_ligands(dock_ligands_t L);
+
+/* ------------------------------------------------------------------------
+ * Score and gradient of arbitrary poses (teacher input, no sampling).
+ * E = sum_i trilerp(M[t_i], x_i) + 10 |x_i - clamp(x_i)|_1 + E_intra, and
+ * dE/dq by the chain rule (Discussion item 3).
+ *   pose_lig  device [n_poses] int32 ligand of each pose
+ *   q         device [n_poses * q_stride]
+ *   E         device [n_poses]
+ *   dEdq      device [n_poses * q_stride] or NULL (entries >= 6 + n_t untouched)
+ *   xyz_out   device [n_poses * xyz_stride] or NULL: world coordinates in the
+ *             caller's atom order, xyz_stride >= 3 * max_atoms
+ * Each ligand's pocket is pockets[pocket_index].
+ * ---------------------------------------------------------------------- */
+int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
+                    int64_t n_poses, const int32_t* pose_lig, const float* q, int32_t q_stride,
+                    float* E, float* dEdq, float* xyz_out, int32_t xyz_stride, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Sampling (Methods, "Conformation sampling"; Fig. 2).  Each trajectory
+ * starts from random DOFs, then each MC step resamples one scalar DOF
+ * uniformly over its range, refines with n_local local steps (Adam, lr 0.1,
+ * moments reset per MC step; or Armijo line search) and accepts iff
+ * u < exp(-mc_beta * dE).  Randoms: Philox4x32-10 with key (ligand, seed)
+ * and counter (trajectory, step, purpose, block).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_traj;           /* trajectories per ligand, >= 1 */
+  int32_t n_steps;          /* MC steps, >= 0 */
+  int32_t n_local;          /* local steps per MC step, >= 0 */
+  int32_t local_opt;        /* DOCK_LOCAL_ADAM or DOCK_LOCAL_LINESEARCH */
+  float lr, beta1, beta2, eps;
+  float mc_beta;            /* 0.069 */
+  uint32_t seed;
+  int32_t form;             /* DOCK_FORM_PLAIN: one launch per ligand;
+                               DOCK_FORM_BATCHED: ragged-packed persistent launches */
+  int32_t use_graph;        /* batched: replay the launch sequence as a hipGraph */
+  int32_t steps_per_launch; /* 0: all steps in one launch per bucket */
+  int32_t record_trace;     /* store q, E, dE/dq of every evaluation (tests) */
+  int32_t lanes_per_pose;   /* 0: planner choice; else 16, 32 or 64 */
+} dock_sample_params;
+
+void dock_sample_params_default(dock_sample_params* p);
+
+/* Creates a run, draws the initial poses, scores them and advances every
+ * trajectory by p->n_steps MC steps.  The run owns its state buffers. */
+int dock_sample(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
+                const dock_sample_params* p, void* stream, dock_run_t* out);
+/* Advances every trajectory by n_steps more MC steps (resume). */
+int dock_run_advance(dock_run_t r, int32_t n_steps, void* stream);
+
+typedef struct {
+  int32_t n_ligands, n_traj, q_stride, step;
+  float* q_cur;       /* device [n_ligands * n_traj * q_stride] */
+  float* E_cur;       /* device [n_ligands * n_traj] */
+  float* q_best;      /* device [n_ligands * n_traj * q_stride] */
+  float* E_best;      /* device [n_ligands * n_traj] */
+  int32_t* n_evals;   /* device [n_ligands * n_traj], evaluations so far */
+  float* trace;       /* device, record_trace only: per trajectory
+                         [trace_cap][2 * q_stride + 1] rows (q, dE/dq, E) */
+  int32_t trace_cap;  /* rows per trajectory */
+} dock_run_view;
+
+int dock_run_view_get(dock_run_t r, dock_run_view* v);
+/* Copies the run's state into caller device buffers laid out as in
+ * dock_run_view (each nullable) on `stream`. */
+int dock_run_copy_state(dock_run_t r, float* q_cur, float* E_cur, float* q_best, float* E_best,
+                        int32_t* n_evals, float* trace, void* stream);
+/* Replaces the trajectory state (checkpoint restore).  Device inputs laid out
+ * as in dock_run_view; `step` is the number of MC steps already taken. */
+int dock_run_set_state(dock_run_t r, const float* q_cur, const float* E_cur, const float* q_best,
+                       const float* E_best, int32_t step, void* stream);
+/* Device time (ms) of the sampler launches of the last dock_sample /
+ * dock_run_advance call, measured with HIP events on the run's stream
+ * (blocks until they complete). */
+int dock_run_kernel_ms(dock_run_t r, float* ms);
+/* Per-launch record of the last dock_sample / dock_run_advance call.
+ * Durations come from HIP events recorded around each sampler launch on the
+ * run's stream (not available when the launches were replayed as a graph:
+ * ms = -1 then).  bucket: index of the lane configuration (see dock_run_plan). */
+typedef struct {
+  int32_t bucket, lanes_per_pose, atoms_per_lane, block, grid, n_items, init, step_count;
+  float ms;
+} dock_launch_stat;
+int dock_run_launch_stats(dock_run_t r, dock_launch_stat* out, int32_t cap, int32_t* n);
+/* Lane configuration chosen for each ligand: lig_bucket [n_ligands] (host,
+ * nullable); bucket_lanes / bucket_apl [n_buckets] (host, nullable). */
+int dock_run_plan(dock_run_t r, int32_t* lig_bucket, int32_t* bucket_lanes, int32_t* bucket_apl,
+                  int32_t* n_buckets);
+int dock_free_run(dock_run_t r);
+
+/* ------------------------------------------------------------------------
+ * Best poses (Methods, "Conformation sampling": rank, cluster, top N;
+ * E_screen = E / (1 + w_tor N_tor), Methods E_screen).  Per ligand, the
+ * n_traj candidates (E_best, q_best) are ranked by E (ties: lower
+ * trajectory), then greedily kept unless their heavy-atom RMSD (atom order,
+ * no superposition) to a kept pose is below rmsd_cluster, up to top_n.
+ * Outputs are device arrays [n_ligands * top_n (* q_stride | * xyz_stride)];
+ * unused slots get E = +inf and idx = -1.
+ * ---------------------------------------------------------------------- */
+int dock_best_poses(dock_ligands_t L, int32_t n_traj, const float* E_best, const float* q_best,
+                    int32_t q_stride, int32_t top_n, float rmsd_cluster, float w_tor,
+                    float* E_out, float* E_screen, float* q_out, int32_t* idx_out,
+                    float* xyz_out, int32_t xyz_stride, int32_t* n_out, void* stream);
+
+/* Raw Philox4x32-10 blocks from the sampler's generator (Salmon et al.,
+ * SC'11): out[4i..4i+3] = Philox(counter = counters[4i..4i+3], key = (k0, k1)).
+ * counters, out: device [n * 4] uint32.  For checking the random stream. */
+int dock_philox(const uint32_t* counters, uint32_t k0, uint32_t k1, int64_t n, uint32_t* out,
+                void* stream);
+
+/* Utilities */
+const char* dock_last_error(void);
+int dock_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DOCK_H */

@@ -1,0 +1,1101 @@
+// C ABI of libdock: argument validation, handle ownership, device upload,
+// the sampling planner (lane configuration per ligand, ragged packing into
+// work items, persistent launches, hipGraph replay) and the launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dock_device.h"
+#include "dock_internal.h"
+#include "dock_kernels.h"
+
+using namespace dock;
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? DOCK_E_OOM : DOCK_E_HIP,                  \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+  } while (0)
+
+template <class T>
+static hipError_t dev_alloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+}
+
+template <class T>
+static void dev_free(T*& p) {
+  if (p) (void)hipFree(const_cast<void*>(reinterpret_cast<const void*>(p)));
+  p = nullptr;
+}
+
+// ---------------------------------------------------------------- handles
+
+struct dock_pocket_s {
+  PocketDev dev{};   // host copy of the device descriptor
+  int n_rec = 0;
+  float4* d_rec = nullptr;
+  float* d_M = nullptr;
+  float* d_G = nullptr;
+};
+
+struct dock_ligands_s {
+  std::vector<LigandHost> host;
+  std::vector<LigDev> h_ligs;
+  int n = 0, max_atoms = 0, max_tors = 0, max_pairs = 0, max_frags = 0;
+  long long total_atoms = 0;
+  bool host_only = false;
+  LigDev* d_ligs = nullptr;
+  float4* d_atoms = nullptr;
+  FragDev* d_frags = nullptr;
+  TorsDev* d_tors = nullptr;
+  PairRec* d_pairs = nullptr;
+  LigandArrays arrays() const { return LigandArrays{d_ligs, d_atoms, d_frags, d_tors, d_pairs}; }
+};
+
+// Device tables of PocketDev, cached per ordered list of pocket handles.
+static std::mutex g_tab_mu;
+static std::map<std::vector<dock_pocket_t>, PocketDev*> g_tables;
+
+static int pocket_table(const dock_pocket_t* pockets, int n, const PocketDev** out) {
+  std::vector<dock_pocket_t> key(pockets, pockets + n);
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  auto it = g_tables.find(key);
+  if (it != g_tables.end()) {
+    *out = it->second;
+    return DOCK_OK;
+  }
+  std::vector<PocketDev> h(n);
+  for (int i = 0; i < n; ++i) h[i] = pockets[i]->dev;
+  PocketDev* d = nullptr;
+  HIP_TRY(dev_alloc(&d, size_t(n)));
+  hipError_t e = hipMemcpy(d, h.data(), sizeof(PocketDev) * n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    dev_free(d);
+    return fail(DOCK_E_HIP, std::string("pocket table upload: ") + hipGetErrorString(e));
+  }
+  g_tables[key] = d;
+  *out = d;
+  return DOCK_OK;
+}
+
+static void drop_tables_with(dock_pocket_t p) {
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  for (auto it = g_tables.begin(); it != g_tables.end();) {
+    if (std::find(it->first.begin(), it->first.end(), p) != it->first.end()) {
+      (void)hipDeviceSynchronize();
+      dev_free(it->second);
+      it = g_tables.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- lane plan
+
+struct LaneCfg {
+  int lpp, apl;
+};
+
+// Smallest group that gives every DOF, fragment and atom (two per lane above
+// 64 atoms) a lane.
+static LaneCfg lane_cfg(const LigDev& lg, int force_lpp) {
+  LaneCfg c;
+  c.apl = lg.n_atoms > 64 ? 2 : 1;
+  const int need = std::max({(lg.n_atoms + c.apl - 1) / c.apl, lg.n_dof, lg.n_frags});
+  c.lpp = need <= 16 ? 16 : (need <= 32 ? 32 : 64);
+  if (c.apl == 2) c.lpp = 64;
+  if (force_lpp > c.lpp && c.apl == 1) c.lpp = force_lpp;
+  return c;
+}
+
+extern "C" {
+
+const char* dock_last_error(void) { return g_err.c_str(); }
+int dock_abi_version(void) { return DOCK_ABI_VERSION; }
+
+// ================================================================ pocket
+
+int dock_load_pocket(const dock_pocket_desc* d, void* stream, dock_pocket_t* out) {
+  if (!d || !out) return fail(DOCK_E_ARG, "null argument");
+  if (d->n_atoms < 0 || (d->n_atoms > 0 && (!d->xyz || !d->type)))
+    return fail(DOCK_E_ARG, "bad receptor arrays");
+  if (d->preset != DOCK_PRESET_TRIDS && d->preset != DOCK_PRESET_VINA)
+    return fail(DOCK_E_ARG, "unknown preset");
+  if (!(d->spacing > 0.f) || !std::isfinite(d->spacing)) return fail(DOCK_E_ARG, "bad spacing");
+  for (int c = 0; c < 3; ++c) {
+    if (d->dims[c] < 2 || d->dims[c] > 1024) return fail(DOCK_E_ARG, "grid dims must be in [2, 1024]");
+    if (!std::isfinite(d->origin[c])) return fail(DOCK_E_ARG, "bad origin");
+  }
+  for (int i = 0; i < d->n_atoms; ++i) {
+    if (d->type[i] >= kTypes) return fail(DOCK_E_ARG, "receptor type out of range");
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(d->xyz[3 * i + c])) return fail(DOCK_E_ARG, "non-finite receptor coordinate");
+  }
+  const long long nodes = (long long)d->dims[0] * d->dims[1] * d->dims[2];
+  dock_pocket_s* p = new (std::nothrow) dock_pocket_s;
+  if (!p) return fail(DOCK_E_OOM, "host allocation");
+  PocketDev& pd = p->dev;
+  int K = 0;
+  preset_weights(d->preset, pd.w, &K);
+  if (d->weights)
+    for (int k = 0; k < K; ++k) {
+      if (!std::isfinite(d->weights[k])) {
+        delete p;
+        return fail(DOCK_E_ARG, "non-finite weight");
+      }
+      pd.w[k] = d->weights[k];
+    }
+  for (int k = K; k < kMaxTerms; ++k) pd.w[k] = 0.f;
+  pd.preset = d->preset;
+  pd.n_terms = K;
+  for (int c = 0; c < 3; ++c) {
+    pd.grid.origin[c] = d->origin[c];
+    pd.grid.dims[c] = d->dims[c];
+    pd.grid.hi[c] = float(double(d->origin[c]) + double(d->spacing) * (d->dims[c] - 1));
+  }
+  pd.grid.spacing = d->spacing;
+  pd.grid.inv_spacing = 1.0f / d->spacing;
+  p->n_rec = d->n_atoms;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<float4> rec(std::max(1, d->n_atoms));
+  for (int i = 0; i < d->n_atoms; ++i) {
+    int bits = d->type[i];
+    rec[i] = make_float4(d->xyz[3 * i], d->xyz[3 * i + 1], d->xyz[3 * i + 2], 0.f);
+    std::memcpy(&rec[i].w, &bits, 4);
+  }
+  auto cleanup = [&](int code, const std::string& m) {
+    dev_free(p->d_rec);
+    dev_free(p->d_M);
+    dev_free(p->d_G);
+    delete p;
+    return fail(code, m);
+  };
+  hipError_t e = dev_alloc(&p->d_rec, rec.size());
+  if (e == hipSuccess) e = dev_alloc(&p->d_M, size_t(kTypes) * nodes);
+  if (e == hipSuccess && d->keep_per_term) e = dev_alloc(&p->d_G, size_t(kTypes) * K * nodes);
+  if (e != hipSuccess) return cleanup(DOCK_E_OOM, std::string("map allocation: ") + hipGetErrorString(e));
+  e = hipMemcpy(p->d_rec, rec.data(), sizeof(float4) * rec.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return cleanup(DOCK_E_HIP, std::string("receptor upload: ") + hipGetErrorString(e));
+  MapArgs a{};
+  a.rec = p->d_rec;
+  a.n_rec = d->n_atoms;
+  a.grid = pd.grid;
+  a.preset = d->preset;
+  a.n_terms = K;
+  for (int k = 0; k < kMaxTerms; ++k) a.w[k] = pd.w[k];
+  type_pair_table(d->preset, a.tab);
+  a.G = p->d_G;
+  a.M = p->d_M;
+  e = launch_map_build(a, s);
+  if (e != hipSuccess) return cleanup(DOCK_E_HIP, std::string("map build: ") + hipGetErrorString(e));
+  pd.M = p->d_M;
+  pd.G = p->d_G;
+  *out = p;
+  return DOCK_OK;
+}
+
+int dock_pocket_maps(dock_pocket_t p, int32_t per_term, float** dev_ptr, int64_t* n_floats) {
+  if (!p || !dev_ptr) return fail(DOCK_E_ARG, "null argument");
+  const long long nodes = (long long)p->dev.grid.dims[0] * p->dev.grid.dims[1] * p->dev.grid.dims[2];
+  if (per_term) {
+    if (!p->d_G) return fail(DOCK_E_ARG, "per-term maps were not kept");
+    *dev_ptr = p->d_G;
+    if (n_floats) *n_floats = (long long)kTypes * p->dev.n_terms * nodes;
+  } else {
+    *dev_ptr = p->d_M;
+    if (n_floats) *n_floats = (long long)kTypes * nodes;
+  }
+  return DOCK_OK;
+}
+
+int dock_pocket_copy_maps(dock_pocket_t p, int32_t per_term, float* dst, void* stream) {
+  float* src = nullptr;
+  int64_t n = 0;
+  int rc = dock_pocket_maps(p, per_term, &src, &n);
+  if (rc) return rc;
+  if (!dst) return fail(DOCK_E_ARG, "null destination");
+  HIP_TRY(hipMemcpyAsync(dst, src, size_t(n) * sizeof(float), hipMemcpyDeviceToDevice,
+                         reinterpret_cast<hipStream_t>(stream)));
+  return DOCK_OK;
+}
+
+int dock_pocket_terms(dock_pocket_t p, int32_t* preset, int32_t* n_terms, float* weights) {
+  if (!p) return fail(DOCK_E_ARG, "null pocket");
+  if (preset) *preset = p->dev.preset;
+  if (n_terms) *n_terms = p->dev.n_terms;
+  if (weights)
+    for (int k = 0; k < p->dev.n_terms; ++k) weights[k] = p->dev.w[k];
+  return DOCK_OK;
+}
+
+int dock_free_pocket(dock_pocket_t p) {
+  if (!p) return DOCK_OK;
+  drop_tables_with(p);
+  (void)hipDeviceSynchronize();
+  dev_free(p->d_rec);
+  dev_free(p->d_M);
+  dev_free(p->d_G);
+  delete p;
+  return DOCK_OK;
+}
+
+// ================================================================ ligands
+
+static void free_ligand_device(dock_ligands_s* L) {
+  dev_free(L->d_ligs);
+  dev_free(L->d_atoms);
+  dev_free(L->d_frags);
+  dev_free(L->d_tors);
+  dev_free(L->d_pairs);
+}
+
+static int bit_length(int v) {
+  int b = 0;
+  while (v > 0) {
+    ++b;
+    v >>= 1;
+  }
+  return b;
+}
+
+int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* out) {
+  (void)stream;
+  if (!d || !out) return fail(DOCK_E_ARG, "null argument");
+  if (d->n_ligands < 1) return fail(DOCK_E_ARG, "n_ligands must be >= 1");
+  if (!d->atom_off || !d->element || !d->n_h || !d->xyz || !d->bond_off)
+    return fail(DOCK_E_ARG, "null ligand array");
+  if (d->atom_off[0] != 0 || d->bond_off[0] != 0) return fail(DOCK_E_ARG, "offsets must start at 0");
+  for (int i = 0; i < d->n_ligands; ++i)
+    if (d->atom_off[i + 1] < d->atom_off[i] || d->bond_off[i + 1] < d->bond_off[i])
+      return fail(DOCK_E_ARG, "offsets must be non-decreasing");
+  if (d->bond_off[d->n_ligands] > 0 && (!d->bonds || !d->rotatable))
+    return fail(DOCK_E_ARG, "null bond arrays");
+  dock_ligands_s* L = new (std::nothrow) dock_ligands_s;
+  if (!L) return fail(DOCK_E_OOM, "host allocation");
+  L->n = d->n_ligands;
+  L->host_only = d->host_only != 0;
+  L->host.resize(L->n);
+  std::string err;
+  for (int i = 0; i < L->n; ++i) {
+    const int a0 = d->atom_off[i], b0 = d->bond_off[i];
+    const int n = d->atom_off[i + 1] - a0, nb = d->bond_off[i + 1] - b0;
+    int rc = prepare_ligand(n, d->element + a0, d->n_h + a0, d->xyz + 3 * size_t(a0), nb,
+                            nb ? d->bonds + 2 * size_t(b0) : nullptr, nb ? d->rotatable + b0 : nullptr,
+                            d->box_min ? d->box_min + 3 * size_t(i) : nullptr,
+                            d->box_max ? d->box_max + 3 * size_t(i) : nullptr, L->host[i], err);
+    if (rc != DOCK_OK) {
+      delete L;
+      return fail(rc, "ligand " + std::to_string(i) + ": " + err);
+    }
+    L->host[i].pocket = d->pocket_index ? d->pocket_index[i] : 0;
+    if (L->host[i].pocket < 0) {
+      delete L;
+      return fail(DOCK_E_ARG, "negative pocket index");
+    }
+  }
+  // pack (DFS atom order)
+  std::vector<float4> atoms;
+  std::vector<FragDev> frags;
+  std::vector<TorsDev> tors;
+  std::vector<PairRec> pairs;
+  TypePair tab[kTypes * kTypes];
+  type_pair_table(DOCK_PRESET_TRIDS, tab);
+  L->h_ligs.resize(L->n);
+  for (int i = 0; i < L->n; ++i) {
+    const LigandHost& H = L->host[i];
+    LigDev& g = L->h_ligs[i];
+    std::memset(&g, 0, sizeof g);
+    g.n_atoms = H.n_atoms;
+    g.n_tors = H.n_tors;
+    g.n_frags = H.n_frags;
+    g.n_pairs = int(H.pair_i.size());
+    g.atom_off = int(atoms.size());
+    g.pair_off = int(pairs.size());
+    g.frag_off = int(frags.size());
+    g.tors_off = int(tors.size());
+    g.pocket = H.pocket;
+    g.n_dof = 6 + H.n_tors;
+    g.fk_rounds = bit_length(H.height);
+    for (int c = 0; c < 3; ++c) {
+      g.c0[c] = float(H.c0[c]);
+      g.box_min[c] = H.box_min[c];
+      g.box_max[c] = H.box_max[c];
+    }
+    for (int na = 0; na < H.n_atoms; ++na) {
+      const int a = H.dfs_atom[na];
+      const int bits = int(H.type[a]) | (H.frag_new[H.atom_frag[a]] << 8) | (a << 16);
+      float4 v = make_float4(H.x0[3 * a], H.x0[3 * a + 1], H.x0[3 * a + 2], 0.f);
+      std::memcpy(&v.w, &bits, 4);
+      atoms.push_back(v);
+    }
+    std::vector<int> frag_tors(H.n_frags, -1);
+    for (int k = 0; k < H.n_tors; ++k) frag_tors[H.tors_frag[k]] = k;
+    for (int nf = 0; nf < H.n_frags; ++nf) {
+      const int f = H.dfs_frag[nf];
+      FragDev fd{};
+      if (H.frag_parent[f] < 0) {
+        fd.parent = -1;
+        fd.dof = -1;
+      } else {
+        const int k = frag_tors[f];
+        const int a = H.tors_a[k], b = H.tors_b[k];
+        double u[3], n2 = 0;
+        for (int c = 0; c < 3; ++c) {
+          u[c] = double(H.x0[3 * b + c]) - double(H.x0[3 * a + c]);
+          n2 += u[c] * u[c];
+        }
+        const double inv = 1.0 / std::sqrt(n2);
+        for (int c = 0; c < 3; ++c) {
+          fd.u[c] = float(u[c] * inv);
+          fd.xb[c] = H.x0[3 * b + c];
+        }
+        fd.parent = H.frag_new[H.frag_parent[f]];
+        fd.dof = 6 + k;
+      }
+      frags.push_back(fd);
+    }
+    // torsion k moves the DFS subtree of its child fragment: a contiguous range
+    std::vector<int> first(H.n_frags, 0), last(H.n_frags, 0);  // atom range per new frag id
+    {
+      std::vector<int> start(H.n_frags, -1), stop(H.n_frags, -1);
+      for (int na = 0; na < H.n_atoms; ++na) {
+        const int nf = H.frag_new[H.atom_frag[H.dfs_atom[na]]];
+        if (start[nf] < 0) start[nf] = na;
+        stop[nf] = na + 1;
+      }
+      // subtree end = max stop over the DFS subtree; in pre-order the subtree
+      // of nf is nf .. nf + size - 1
+      std::vector<int> size(H.n_frags, 1);
+      for (int nf = H.n_frags - 1; nf >= 1; --nf) {
+        const int par = frags[g.frag_off + nf].parent;
+        size[par] += size[nf];
+      }
+      for (int nf = 0; nf < H.n_frags; ++nf) {
+        first[nf] = start[nf];
+        last[nf] = stop[nf + size[nf] - 1];
+      }
+    }
+    for (int k = 0; k < H.n_tors; ++k) {
+      const int nf = H.frag_new[H.tors_frag[k]];
+      TorsDev t{};
+      t.sub_begin = first[nf];
+      t.sub_end = last[nf];
+      t.a = H.atom_new[H.tors_a[k]];
+      t.b = H.atom_new[H.tors_b[k]];
+      tors.push_back(t);
+    }
+    for (size_t p = 0; p < H.pair_i.size(); ++p) {
+      const int i0 = H.atom_new[H.pair_i[p]], j0 = H.atom_new[H.pair_j[p]];
+      const int ti = H.type[H.pair_i[p]], tj = H.type[H.pair_j[p]];
+      const TypePair& tp = tab[ti * kTypes + tj];
+      PairRec pr;
+      pr.w = uint32_t(i0) | (uint32_t(j0) << 8) | (uint32_t(ti) << 16) | (uint32_t(tj) << 20) |
+             (tp.flags << 24);
+      pr.rsum = tp.rsum;
+      pairs.push_back(pr);
+    }
+    L->max_atoms = std::max(L->max_atoms, H.n_atoms);
+    L->max_tors = std::max(L->max_tors, H.n_tors);
+    L->max_pairs = std::max(L->max_pairs, g.n_pairs);
+    L->max_frags = std::max(L->max_frags, H.n_frags);
+    L->total_atoms += H.n_atoms;
+  }
+  if (!L->host_only) {
+    hipError_t e = dev_alloc(&L->d_ligs, L->h_ligs.size());
+    if (e == hipSuccess) e = dev_alloc(&L->d_atoms, atoms.size());
+    if (e == hipSuccess) e = dev_alloc(&L->d_frags, frags.size());
+    if (e == hipSuccess) e = dev_alloc(&L->d_tors, tors.size());
+    if (e == hipSuccess) e = dev_alloc(&L->d_pairs, pairs.size());
+    if (e == hipSuccess && !L->h_ligs.empty())
+      e = hipMemcpy(L->d_ligs, L->h_ligs.data(), sizeof(LigDev) * L->h_ligs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !atoms.empty())
+      e = hipMemcpy(L->d_atoms, atoms.data(), sizeof(float4) * atoms.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !frags.empty())
+      e = hipMemcpy(L->d_frags, frags.data(), sizeof(FragDev) * frags.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tors.empty())
+      e = hipMemcpy(L->d_tors, tors.data(), sizeof(TorsDev) * tors.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !pairs.empty())
+      e = hipMemcpy(L->d_pairs, pairs.data(), sizeof(PairRec) * pairs.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      free_ligand_device(L);
+      delete L;
+      return fail(e == hipErrorOutOfMemory ? DOCK_E_OOM : DOCK_E_HIP,
+                  std::string("ligand upload: ") + hipGetErrorString(e));
+    }
+  }
+  *out = L;
+  return DOCK_OK;
+}
+
+int dock_ligand_info(dock_ligands_t L, int32_t lig, dock_ligand_info_t* info) {
+  if (!L || !info) return fail(DOCK_E_ARG, "null argument");
+  if (lig < 0 || lig >= L->n) return fail(DOCK_E_ARG, "ligand index out of range");
+  const LigandHost& H = L->host[lig];
+  info->n_atoms = H.n_atoms;
+  info->n_tors = H.n_tors;
+  info->n_frags = H.n_frags;
+  info->n_pairs = int(H.pair_i.size());
+  info->root = H.root;
+  info->height = H.height;
+  info->pocket = H.pocket;
+  for (int c = 0; c < 3; ++c) {
+    info->c0[c] = float(H.c0[c]);
+    info->box_min[c] = H.box_min[c];
+    info->box_max[c] = H.box_max[c];
+  }
+  return DOCK_OK;
+}
+
+int dock_ligand_topology(dock_ligands_t L, int32_t lig, uint8_t* type, int32_t* atom_frag,
+                         int32_t* frag_parent, int32_t* tors_frag, int32_t* tors_atoms, int32_t* pairs,
+                         int32_t* bfs) {
+  if (!L) return fail(DOCK_E_ARG, "null argument");
+  if (lig < 0 || lig >= L->n) return fail(DOCK_E_ARG, "ligand index out of range");
+  const LigandHost& H = L->host[lig];
+  if (type) std::copy(H.type.begin(), H.type.end(), type);
+  if (atom_frag) std::copy(H.atom_frag.begin(), H.atom_frag.end(), atom_frag);
+  if (frag_parent) std::copy(H.frag_parent.begin(), H.frag_parent.end(), frag_parent);
+  if (tors_frag) std::copy(H.tors_frag.begin(), H.tors_frag.end(), tors_frag);
+  if (tors_atoms)
+    for (int k = 0; k < H.n_tors; ++k) {
+      tors_atoms[2 * k] = H.tors_a[k];
+      tors_atoms[2 * k + 1] = H.tors_b[k];
+    }
+  if (pairs)
+    for (size_t p = 0; p < H.pair_i.size(); ++p) {
+      pairs[2 * p] = H.pair_i[p];
+      pairs[2 * p + 1] = H.pair_j[p];
+    }
+  if (bfs) std::copy(H.bfs.begin(), H.bfs.end(), bfs);
+  return DOCK_OK;
+}
+
+int dock_ligands_count(dock_ligands_t L, int32_t* n_ligands, int32_t* max_atoms, int32_t* max_tors,
+                       int64_t* total_atoms) {
+  if (!L) return fail(DOCK_E_ARG, "null argument");
+  if (n_ligands) *n_ligands = L->n;
+  if (max_atoms) *max_atoms = L->max_atoms;
+  if (max_tors) *max_tors = L->max_tors;
+  if (total_atoms) *total_atoms = L->total_atoms;
+  return DOCK_OK;
+}
+
+int dock_free_ligands(dock_ligands_t L) {
+  if (!L) return DOCK_OK;
+  if (!L->host_only) (void)hipDeviceSynchronize();
+  free_ligand_device(L);
+  delete L;
+  return DOCK_OK;
+}
+
+// ================================================================ score
+
+static int check_pockets(const dock_pocket_t* pockets, int n_pockets, dock_ligands_t L) {
+  if (!pockets || n_pockets < 1) return fail(DOCK_E_ARG, "no pockets");
+  for (int i = 0; i < n_pockets; ++i)
+    if (!pockets[i]) return fail(DOCK_E_ARG, "null pocket handle");
+  for (int i = 0; i < L->n; ++i)
+    if (L->host[i].pocket >= n_pockets) return fail(DOCK_E_ARG, "ligand pocket index out of range");
+  if (L->host_only) return fail(DOCK_E_ARG, "ligand handle was loaded host_only");
+  return DOCK_OK;
+}
+
+int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L, int64_t n_poses,
+                    const int32_t* pose_lig, const float* q, int32_t q_stride, float* E, float* dEdq,
+                    float* xyz_out, int32_t xyz_stride, void* stream) {
+  if (!L) return fail(DOCK_E_ARG, "null ligands");
+  int rc = check_pockets(pockets, n_pockets, L);
+  if (rc) return rc;
+  if (n_poses < 0) return fail(DOCK_E_ARG, "negative n_poses");
+  if (n_poses == 0) return DOCK_OK;
+  if (!pose_lig || !q || !E) return fail(DOCK_E_ARG, "null pose array");
+  if (q_stride < 6 + L->max_tors) return fail(DOCK_E_ARG, "q_stride < 6 + max torsions");
+  if (xyz_out && xyz_stride < 3 * L->max_atoms) return fail(DOCK_E_ARG, "xyz_stride < 3 * max atoms");
+  const PocketDev* tab = nullptr;
+  rc = pocket_table(pockets, n_pockets, &tab);
+  if (rc) return rc;
+  // one lane configuration wide enough for every ligand of the handle
+  int lpp = 16, apl = 1;
+  for (const LigDev& g : L->h_ligs) {
+    LaneCfg c = lane_cfg(g, 0);
+    lpp = std::max(lpp, c.lpp);
+    apl = std::max(apl, c.apl);
+  }
+  if (apl == 2) lpp = 64;
+  if (score_lds_bytes(lpp, apl, L->max_pairs) > 64 * 1024)
+    return fail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
+  ScoreArgs a{};
+  a.L = L->arrays();
+  a.pockets = tab;
+  a.n_ligands = L->n;
+  a.n_pockets = n_pockets;
+  a.n_poses = n_poses;
+  a.pose_lig = pose_lig;
+  a.q = q;
+  a.q_stride = q_stride;
+  a.E = E;
+  a.dEdq = dEdq;
+  a.xyz = xyz_out;
+  a.xyz_stride = xyz_stride;
+  a.max_pairs = L->max_pairs;
+  HIP_TRY(launch_score(a, lpp, apl, reinterpret_cast<hipStream_t>(stream)));
+  return DOCK_OK;
+}
+
+// ================================================================ sampling
+
+void dock_sample_params_default(dock_sample_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->n_traj = 64;
+  p->n_steps = 100;
+  p->n_local = 10;
+  p->local_opt = DOCK_LOCAL_ADAM;
+  p->lr = 0.1f;
+  p->beta1 = 0.9f;
+  p->beta2 = 0.999f;
+  p->eps = 1e-8f;
+  p->mc_beta = 0.069f;
+  p->seed = 0;
+  p->form = DOCK_FORM_BATCHED;
+  p->use_graph = 1;
+  p->steps_per_launch = 0;
+  p->record_trace = 0;
+  p->lanes_per_pose = 0;
+}
+
+struct Bucket {
+  int lpp = 0, apl = 0, block = 256, max_pairs = 0;
+  int item_off = 0, n_items = 0;   // batched: this bucket's items
+  int grid = 0;                    // batched: persistent grid
+  std::vector<int> ligs;
+};
+
+struct dock_run_s {
+  dock_ligands_t L = nullptr;
+  std::vector<dock_pocket_t> pockets;
+  const PocketDev* table = nullptr;
+  dock_sample_params p{};
+  int n_lig = 0, T = 0, q_stride = 0, step = 0, trace_cap = 0;
+  float *q_cur = nullptr, *E_cur = nullptr, *q_best = nullptr, *E_best = nullptr, *trace = nullptr;
+  int* n_evals = nullptr;
+  int* d_step = nullptr;
+  int2* d_items = nullptr;
+  int* d_queue = nullptr;
+  int n_queue = 0;
+  std::vector<Bucket> buckets;
+  // plain form: per ligand (bucket index, first item, item count)
+  std::vector<int> lig_bucket, lig_item_off, lig_n_items;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_steps = -1;
+  // per-launch timing of the last call (eager launches only)
+  struct Launch {
+    dock_launch_stat st;
+    hipEvent_t a, b;
+  };
+  std::vector<Launch> launches;
+  std::vector<hipEvent_t> event_pool;
+  size_t events_used = 0;
+  bool recording = false;
+};
+
+static hipEvent_t pool_event(dock_run_s* r) {
+  if (r->events_used == r->event_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    r->event_pool.push_back(e);
+  }
+  return r->event_pool[r->events_used++];
+}
+
+// Launch one sampler grid, bracketed by events when recording.
+static hipError_t timed_launch(dock_run_s* r, const SampleArgs& a, int bucket, int lpp, int apl, int grid,
+                               int block, hipStream_t s) {
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (r->recording) {
+    ea = pool_event(r);
+    eb = pool_event(r);
+    if (ea) (void)hipEventRecord(ea, s);
+  }
+  hipError_t e = launch_sample(a, lpp, apl, grid, block, s);
+  if (r->recording && ea && eb) {
+    (void)hipEventRecord(eb, s);
+    dock_run_s::Launch L;
+    L.st.bucket = bucket;
+    L.st.lanes_per_pose = lpp;
+    L.st.atoms_per_lane = apl;
+    L.st.block = block;
+    L.st.grid = grid;
+    L.st.n_items = a.n_items;
+    L.st.init = a.init;
+    L.st.step_count = a.step_count;
+    L.st.ms = -1.f;
+    L.a = ea;
+    L.b = eb;
+    r->launches.push_back(L);
+  }
+  return e;
+}
+
+static void free_run(dock_run_s* r) {
+  for (hipEvent_t e : r->event_pool) (void)hipEventDestroy(e);
+  if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
+  if (r->graph) (void)hipGraphDestroy(r->graph);
+  if (r->ev0) (void)hipEventDestroy(r->ev0);
+  if (r->ev1) (void)hipEventDestroy(r->ev1);
+  dev_free(r->q_cur);
+  dev_free(r->E_cur);
+  dev_free(r->q_best);
+  dev_free(r->E_best);
+  dev_free(r->trace);
+  dev_free(r->n_evals);
+  dev_free(r->d_step);
+  dev_free(r->d_items);
+  dev_free(r->d_queue);
+  delete r;
+}
+
+static SampleArgs base_args(const dock_run_s* r) {
+  SampleArgs a{};
+  a.L = r->L->arrays();
+  a.pockets = r->table;
+  a.step_base = r->d_step;
+  a.n_traj = r->T;
+  a.q_stride = r->q_stride;
+  a.n_local = r->p.n_local;
+  a.local_opt = r->p.local_opt;
+  a.lr = r->p.lr;
+  a.b1 = r->p.beta1;
+  a.b2 = r->p.beta2;
+  a.eps = r->p.eps;
+  a.mc_beta = r->p.mc_beta;
+  a.seed = r->p.seed;
+  a.q_cur = r->q_cur;
+  a.E_cur = r->E_cur;
+  a.q_best = r->q_best;
+  a.E_best = r->E_best;
+  a.n_evals = r->n_evals;
+  a.trace = r->trace;
+  a.trace_cap = r->trace_cap;
+  return a;
+}
+
+// Enqueue the launches of one phase: init (steps = 0) or `steps` MC steps.
+static hipError_t enqueue_phase(dock_run_s* r, bool init, int steps, hipStream_t s) {
+  const int chunk = (init || r->p.steps_per_launch <= 0) ? std::max(steps, 1)
+                                                          : r->p.steps_per_launch;
+  const int n_chunks = init ? 1 : (steps + chunk - 1) / chunk;
+  hipError_t e = hipSuccess;
+  if (r->p.form == DOCK_FORM_BATCHED) {
+    const int need = n_chunks * int(r->buckets.size());
+    if (need > r->n_queue) return hipErrorInvalidValue;
+    e = launch_fill_int(r->d_queue, need, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  for (int c = 0; c < n_chunks; ++c) {
+    SampleArgs a = base_args(r);
+    a.init = init ? 1 : 0;
+    a.step_off = init ? 0 : c * chunk;
+    a.step_count = init ? 0 : std::min(chunk, steps - c * chunk);
+    if (r->p.form == DOCK_FORM_BATCHED) {
+      for (size_t b = 0; b < r->buckets.size(); ++b) {
+        const Bucket& B = r->buckets[b];
+        a.items = r->d_items + B.item_off;
+        a.n_items = B.n_items;
+        a.queue = r->d_queue + c * int(r->buckets.size()) + int(b);
+        a.max_pairs = B.max_pairs;
+        e = timed_launch(r, a, int(b), B.lpp, B.apl, B.grid, B.block, s);
+        if (e != hipSuccess) return e;
+      }
+    } else {
+      for (int l = 0; l < r->n_lig; ++l) {
+        const Bucket& B = r->buckets[r->lig_bucket[l]];
+        a.items = r->d_items + r->lig_item_off[l];
+        a.n_items = r->lig_n_items[l];
+        a.queue = nullptr;
+        a.max_pairs = r->L->h_ligs[l].n_pairs;
+        e = timed_launch(r, a, r->lig_bucket[l], B.lpp, B.apl, r->lig_n_items[l], B.block, s);
+        if (e != hipSuccess) return e;
+      }
+    }
+  }
+  if (!init) e = launch_add_int(r->d_step, steps, s);
+  return e;
+}
+
+static int run_phase(dock_run_s* r, bool init, int steps, hipStream_t s) {
+  if (!init && steps == 0) return DOCK_OK;
+  if (!init && r->p.use_graph && r->p.form == DOCK_FORM_BATCHED) {
+    if (r->graph_steps != steps) {
+      if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
+      if (r->graph) (void)hipGraphDestroy(r->graph);
+      r->gexec = nullptr;
+      r->graph = nullptr;
+      r->graph_steps = -1;
+      hipStream_t cs = nullptr;
+      HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        const bool rec = r->recording;
+        r->recording = false;
+        hipError_t e2 = enqueue_phase(r, false, steps, cs);
+        r->recording = rec;
+        e = hipStreamEndCapture(cs, &r->graph);
+        if (e2 != hipSuccess) e = e2;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&r->gexec, r->graph, nullptr, nullptr, 0);
+      (void)hipStreamDestroy(cs);
+      if (e != hipSuccess) return fail(DOCK_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+      r->graph_steps = steps;
+    }
+    HIP_TRY(hipGraphLaunch(r->gexec, s));
+  } else {
+    HIP_TRY(enqueue_phase(r, init, steps, s));
+  }
+  if (!init) r->step += steps;
+  return DOCK_OK;
+}
+
+// Runs phases between the run's two timing events.
+static int timed_phases(dock_run_s* r, bool init, int steps, hipStream_t s) {
+  r->launches.clear();
+  r->events_used = 0;
+  r->recording = true;
+  HIP_TRY(hipEventRecord(r->ev0, s));
+  int rc = DOCK_OK;
+  if (init) rc = run_phase(r, true, 0, s);
+  if (rc == DOCK_OK) rc = run_phase(r, false, steps, s);
+  if (rc != DOCK_OK) return rc;
+  HIP_TRY(hipEventRecord(r->ev1, s));
+  r->timed = true;
+  return DOCK_OK;
+}
+
+static int check_params(const dock_sample_params* p) {
+  if (!p) return fail(DOCK_E_ARG, "null params");
+  if (p->n_traj < 1 || p->n_steps < 0 || p->n_local < 0) return fail(DOCK_E_ARG, "bad counts");
+  if (p->local_opt != DOCK_LOCAL_ADAM && p->local_opt != DOCK_LOCAL_LINESEARCH)
+    return fail(DOCK_E_ARG, "unknown local_opt");
+  if (p->form != DOCK_FORM_PLAIN && p->form != DOCK_FORM_BATCHED) return fail(DOCK_E_ARG, "unknown form");
+  if (p->lanes_per_pose != 0 && p->lanes_per_pose != 16 && p->lanes_per_pose != 32 && p->lanes_per_pose != 64)
+    return fail(DOCK_E_ARG, "lanes_per_pose must be 0, 16, 32 or 64");
+  if (!(std::isfinite(p->lr) && std::isfinite(p->beta1) && std::isfinite(p->beta2) &&
+        std::isfinite(p->eps) && std::isfinite(p->mc_beta)))
+    return fail(DOCK_E_ARG, "non-finite sampler constant");
+  if (p->steps_per_launch < 0) return fail(DOCK_E_ARG, "negative steps_per_launch");
+  return DOCK_OK;
+}
+
+int dock_sample(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
+                const dock_sample_params* p, void* stream, dock_run_t* out) {
+  if (!L || !out) return fail(DOCK_E_ARG, "null argument");
+  int rc = check_pockets(pockets, n_pockets, L);
+  if (rc) return rc;
+  rc = check_params(p);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  dock_run_s* r = new (std::nothrow) dock_run_s;
+  if (!r) return fail(DOCK_E_OOM, "host allocation");
+  r->L = L;
+  r->pockets.assign(pockets, pockets + n_pockets);
+  r->p = *p;
+  r->n_lig = L->n;
+  r->T = p->n_traj;
+  r->q_stride = 6 + L->max_tors;
+  r->stream = s;
+  auto bail = [&](int code, const std::string& m) {
+    free_run(r);
+    return fail(code, m);
+  };
+  rc = pocket_table(pockets, n_pockets, &r->table);
+  if (rc) {
+    std::string m = g_err;
+    free_run(r);
+    return fail(rc, m);
+  }
+  // ---- plan: lane configuration per ligand, buckets, work items
+  int dev = 0, n_cu = 256;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n_cu = 256;
+  const int block = 256;
+  std::map<std::pair<int, int>, int> bidx;
+  r->lig_bucket.resize(r->n_lig);
+  for (int l = 0; l < r->n_lig; ++l) {
+    const LaneCfg c = lane_cfg(L->h_ligs[l], p->lanes_per_pose);
+    auto key = std::make_pair(c.lpp, c.apl);
+    auto it = bidx.find(key);
+    if (it == bidx.end()) {
+      Bucket B;
+      B.lpp = c.lpp;
+      B.apl = c.apl;
+      B.block = block;
+      it = bidx.emplace(key, int(r->buckets.size())).first;
+      r->buckets.push_back(B);
+    }
+    Bucket& B = r->buckets[it->second];
+    B.ligs.push_back(l);
+    B.max_pairs = std::max(B.max_pairs, L->h_ligs[l].n_pairs);
+    r->lig_bucket[l] = it->second;
+  }
+  std::vector<int2> items;
+  r->lig_item_off.assign(r->n_lig, 0);
+  r->lig_n_items.assign(r->n_lig, 0);
+  if (p->form == DOCK_FORM_PLAIN) {
+    for (int l = 0; l < r->n_lig; ++l) {
+      const Bucket& B = r->buckets[r->lig_bucket[l]];
+      const int gpb = B.block / B.lpp;
+      r->lig_item_off[l] = int(items.size());
+      for (int t0 = 0; t0 < r->T; t0 += gpb) items.push_back(make_int2(l, t0));
+      r->lig_n_items[l] = int(items.size()) - r->lig_item_off[l];
+    }
+  } else {
+    for (Bucket& B : r->buckets) {
+      const int gpb = B.block / B.lpp;
+      // longest work first: cost ~ pairs + 4 * atoms per evaluation
+      std::vector<int> ligs = B.ligs;
+      std::stable_sort(ligs.begin(), ligs.end(), [&](int x, int y) {
+        const LigDev &gx = L->h_ligs[x], &gy = L->h_ligs[y];
+        return gx.n_pairs + 4 * gx.n_atoms > gy.n_pairs + 4 * gy.n_atoms;
+      });
+      B.item_off = int(items.size());
+      for (int l : ligs)
+        for (int t0 = 0; t0 < r->T; t0 += gpb) items.push_back(make_int2(l, t0));
+      B.n_items = int(items.size()) - B.item_off;
+      const size_t lds = sample_lds_bytes(B.lpp, B.apl, B.block, B.max_pairs);
+      if (lds > 64 * 1024) return bail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
+      const int per_cu = sample_max_blocks_per_cu(B.lpp, B.apl, B.block, lds);
+      B.grid = std::min(B.n_items, per_cu * n_cu);
+    }
+  }
+  for (const Bucket& B : r->buckets)
+    if (sample_lds_bytes(B.lpp, B.apl, B.block, B.max_pairs) > 64 * 1024)
+      return bail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
+  // ---- buffers
+  const size_t nt = size_t(r->n_lig) * r->T;
+  const int chunk = p->steps_per_launch > 0 ? p->steps_per_launch : std::max(1, p->n_steps);
+  r->n_queue = int(r->buckets.size()) * std::max(1, (p->n_steps + chunk - 1) / chunk);
+  hipError_t e = dev_alloc(&r->q_cur, nt * r->q_stride);
+  if (e == hipSuccess) e = dev_alloc(&r->q_best, nt * r->q_stride);
+  if (e == hipSuccess) e = dev_alloc(&r->E_cur, nt);
+  if (e == hipSuccess) e = dev_alloc(&r->E_best, nt);
+  if (e == hipSuccess) e = dev_alloc(&r->n_evals, nt);
+  if (e == hipSuccess) e = dev_alloc(&r->d_step, 1);
+  if (e == hipSuccess) e = dev_alloc(&r->d_items, items.size());
+  if (e == hipSuccess) e = dev_alloc(&r->d_queue, size_t(std::max(1, r->n_queue)));
+  if (e == hipSuccess && p->record_trace) {
+    const int per_step = p->local_opt == DOCK_LOCAL_ADAM ? p->n_local + 1 : 1 + 11 * p->n_local;
+    r->trace_cap = 1 + p->n_steps * per_step;
+    e = dev_alloc(&r->trace, nt * size_t(r->trace_cap) * (2 * r->q_stride + 1));
+  }
+  if (e != hipSuccess) return bail(DOCK_E_OOM, std::string("run allocation: ") + hipGetErrorString(e));
+  e = hipMemcpy(r->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bail(DOCK_E_HIP, std::string("item upload: ") + hipGetErrorString(e));
+  if ((e = hipEventCreate(&r->ev0)) != hipSuccess || (e = hipEventCreate(&r->ev1)) != hipSuccess)
+    return bail(DOCK_E_HIP, std::string("event: ") + hipGetErrorString(e));
+  e = launch_fill_int(r->n_evals, int(nt), 0, s);
+  if (e == hipSuccess) e = launch_fill_int(r->d_step, 1, 0, s);
+  if (e == hipSuccess && r->trace) {
+    // trace rows default to NaN
+    e = hipMemsetAsync(r->trace, 0xff, nt * size_t(r->trace_cap) * (2 * r->q_stride + 1) * sizeof(float), s);
+  }
+  if (e != hipSuccess) return bail(DOCK_E_HIP, std::string("init: ") + hipGetErrorString(e));
+  rc = timed_phases(r, true, p->n_steps, s);
+  if (rc != DOCK_OK) {
+    std::string m = g_err;
+    free_run(r);
+    return fail(rc, m);
+  }
+  *out = r;
+  return DOCK_OK;
+}
+
+int dock_run_advance(dock_run_t r, int32_t n_steps, void* stream) {
+  if (!r) return fail(DOCK_E_ARG, "null run");
+  if (n_steps < 0) return fail(DOCK_E_ARG, "negative n_steps");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int chunk = r->p.steps_per_launch > 0 ? r->p.steps_per_launch : std::max(1, n_steps);
+  const int need = int(r->buckets.size()) * std::max(1, (n_steps + chunk - 1) / chunk);
+  if (need > r->n_queue) {
+    dev_free(r->d_queue);
+    r->n_queue = 0;
+    HIP_TRY(dev_alloc(&r->d_queue, size_t(need)));
+    r->n_queue = need;
+    if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
+    if (r->graph) (void)hipGraphDestroy(r->graph);
+    r->gexec = nullptr;
+    r->graph = nullptr;
+    r->graph_steps = -1;
+  }
+  return timed_phases(r, false, n_steps, s);
+}
+
+int dock_run_view_get(dock_run_t r, dock_run_view* v) {
+  if (!r || !v) return fail(DOCK_E_ARG, "null argument");
+  v->n_ligands = r->n_lig;
+  v->n_traj = r->T;
+  v->q_stride = r->q_stride;
+  v->step = r->step;
+  v->q_cur = r->q_cur;
+  v->E_cur = r->E_cur;
+  v->q_best = r->q_best;
+  v->E_best = r->E_best;
+  v->n_evals = r->n_evals;
+  v->trace = r->trace;
+  v->trace_cap = r->trace_cap;
+  return DOCK_OK;
+}
+
+int dock_run_copy_state(dock_run_t r, float* q_cur, float* E_cur, float* q_best, float* E_best,
+                        int32_t* n_evals, float* trace, void* stream) {
+  if (!r) return fail(DOCK_E_ARG, "null run");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t nt = size_t(r->n_lig) * r->T;
+  const auto D2D = hipMemcpyDeviceToDevice;
+  if (q_cur) HIP_TRY(hipMemcpyAsync(q_cur, r->q_cur, nt * r->q_stride * sizeof(float), D2D, s));
+  if (q_best) HIP_TRY(hipMemcpyAsync(q_best, r->q_best, nt * r->q_stride * sizeof(float), D2D, s));
+  if (E_cur) HIP_TRY(hipMemcpyAsync(E_cur, r->E_cur, nt * sizeof(float), D2D, s));
+  if (E_best) HIP_TRY(hipMemcpyAsync(E_best, r->E_best, nt * sizeof(float), D2D, s));
+  if (n_evals) HIP_TRY(hipMemcpyAsync(n_evals, r->n_evals, nt * sizeof(int), D2D, s));
+  if (trace) {
+    if (!r->trace) return fail(DOCK_E_ARG, "run has no trace");
+    HIP_TRY(hipMemcpyAsync(trace, r->trace, nt * size_t(r->trace_cap) * (2 * r->q_stride + 1) * sizeof(float),
+                           D2D, s));
+  }
+  return DOCK_OK;
+}
+
+int dock_run_set_state(dock_run_t r, const float* q_cur, const float* E_cur, const float* q_best,
+                       const float* E_best, int32_t step, void* stream) {
+  if (!r || !q_cur || !E_cur || !q_best || !E_best) return fail(DOCK_E_ARG, "null argument");
+  if (step < 0) return fail(DOCK_E_ARG, "negative step");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t nt = size_t(r->n_lig) * r->T;
+  HIP_TRY(hipMemcpyAsync(r->q_cur, q_cur, nt * r->q_stride * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(r->q_best, q_best, nt * r->q_stride * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(r->E_cur, E_cur, nt * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(r->E_best, E_best, nt * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(launch_fill_int(r->d_step, 1, step, s));
+  r->step = step;
+  return DOCK_OK;
+}
+
+int dock_run_kernel_ms(dock_run_t r, float* ms) {
+  if (!r || !ms) return fail(DOCK_E_ARG, "null argument");
+  if (!r->timed) return fail(DOCK_E_ARG, "run has no timed launches");
+  HIP_TRY(hipEventSynchronize(r->ev1));
+  HIP_TRY(hipEventElapsedTime(ms, r->ev0, r->ev1));
+  return DOCK_OK;
+}
+
+int dock_run_launch_stats(dock_run_t r, dock_launch_stat* out, int32_t cap, int32_t* n) {
+  if (!r || !n) return fail(DOCK_E_ARG, "null argument");
+  if (!r->launches.empty()) HIP_TRY(hipEventSynchronize(r->launches.back().b));
+  int k = 0;
+  for (auto& L : r->launches) {
+    if (out && k < cap) {
+      dock_launch_stat st = L.st;
+      float ms = -1.f;
+      if (hipEventElapsedTime(&ms, L.a, L.b) == hipSuccess) st.ms = ms;
+      out[k] = st;
+    }
+    ++k;
+  }
+  *n = k;
+  return DOCK_OK;
+}
+
+int dock_run_plan(dock_run_t r, int32_t* lig_bucket, int32_t* bucket_lanes, int32_t* bucket_apl,
+                  int32_t* n_buckets) {
+  if (!r) return fail(DOCK_E_ARG, "null run");
+  if (lig_bucket)
+    for (int l = 0; l < r->n_lig; ++l) lig_bucket[l] = r->lig_bucket[l];
+  for (size_t b = 0; b < r->buckets.size(); ++b) {
+    if (bucket_lanes) bucket_lanes[b] = r->buckets[b].lpp;
+    if (bucket_apl) bucket_apl[b] = r->buckets[b].apl;
+  }
+  if (n_buckets) *n_buckets = int(r->buckets.size());
+  return DOCK_OK;
+}
+
+int dock_free_run(dock_run_t r) {
+  if (!r) return DOCK_OK;
+  (void)hipDeviceSynchronize();
+  free_run(r);
+  return DOCK_OK;
+}
+
+// ================================================================ best poses
+
+int dock_best_poses(dock_ligands_t L, int32_t n_traj, const float* E_best, const float* q_best,
+                    int32_t q_stride, int32_t top_n, float rmsd_cluster, float w_tor, float* E_out,
+                    float* E_screen, float* q_out, int32_t* idx_out, float* xyz_out, int32_t xyz_stride,
+                    int32_t* n_out, void* stream) {
+  if (!L) return fail(DOCK_E_ARG, "null ligands");
+  if (L->host_only) return fail(DOCK_E_ARG, "ligand handle was loaded host_only");
+  if (n_traj < 1 || n_traj > 8192) return fail(DOCK_E_ARG, "n_traj must be in [1, 8192]");
+  if (top_n < 1 || top_n > 32) return fail(DOCK_E_ARG, "top_n must be in [1, 32]");
+  if (!E_best || !q_best) return fail(DOCK_E_ARG, "null candidate arrays");
+  if (q_stride < 6 + L->max_tors) return fail(DOCK_E_ARG, "q_stride < 6 + max torsions");
+  if (xyz_out && xyz_stride < 3 * L->max_atoms) return fail(DOCK_E_ARG, "xyz_stride < 3 * max atoms");
+  if (!std::isfinite(rmsd_cluster) || !std::isfinite(w_tor)) return fail(DOCK_E_ARG, "non-finite parameter");
+  BestArgs a{};
+  a.L = L->arrays();
+  a.n_ligands = L->n;
+  a.n_traj = n_traj;
+  a.q_stride = q_stride;
+  a.E_best = E_best;
+  a.q_best = q_best;
+  a.top_n = top_n;
+  a.rmsd_cut = rmsd_cluster;
+  a.w_tor = w_tor;
+  a.E_out = E_out;
+  a.E_screen = E_screen;
+  a.q_out = q_out;
+  a.idx_out = idx_out;
+  a.xyz_out = xyz_out;
+  a.xyz_stride = xyz_stride;
+  a.n_out = n_out;
+  int tp = 1;
+  while (tp < n_traj) tp <<= 1;
+  a.t_pad = tp;
+  if ((size_t(tp) * 8 + 15) / 16 * 16 + size_t(top_n) * kMaxAtoms * 16 > 64 * 1024)
+    return fail(DOCK_E_LIMIT, "n_traj * top_n too large for the best-pose LDS budget");
+  HIP_TRY(launch_best(a, reinterpret_cast<hipStream_t>(stream)));
+  return DOCK_OK;
+}
+
+int dock_philox(const uint32_t* counters, uint32_t k0, uint32_t k1, int64_t n, uint32_t* out,
+                void* stream) {
+  if (n < 0) return fail(DOCK_E_ARG, "negative n");
+  if (n > 0 && (!counters || !out)) return fail(DOCK_E_ARG, "null array");
+  HIP_TRY(launch_philox(counters, k0, k1, n, out, reinterpret_cast<hipStream_t>(stream)));
+  return DOCK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,556 @@
+// Device building blocks of the docking hot path (gfx950, wave64).
+//
+// A pose is evaluated by a group of LPP lanes (16, 32 or 64) of one
+// wavefront.  Lane roles change through the evaluation:
+//   * lane r holds DOF r (r < 6 + n_t): q, its gradient, optimiser state;
+//   * lane f < n_frags composes fragment f's rigid transform;
+//   * lane r owns atoms APL*r .. APL*r+APL-1 (atoms in fragment DFS order);
+//   * all lanes stride over the intra-ligand pair list.
+// Cross-lane traffic uses shuffles within the group; per-pose coordinates
+// and intra forces live in a small LDS slab private to the group.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dock_internal.h"
+
+namespace dock {
+
+#define DK_INLINE __device__ __forceinline__
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kTwoPi = 6.28318530717958647692f;
+constexpr float kInvTwoPi = 0.15915494309189533577f;
+constexpr float kOutK = 10.0f;
+
+// ------------------------------------------------------------------ sync
+DK_INLINE void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon et al., SC'11: two 32x32->64 multiplies per round, high halves mixed
+// with the other two words and the key, key bumped by Weyl constants.
+DK_INLINE uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+DK_INLINE float u01(uint32_t x) { return float(x >> 8) * 5.9604644775390625e-8f; }
+DK_INLINE uint32_t pick4(uint4 w, int i) {
+  return i == 0 ? w.x : (i == 1 ? w.y : (i == 2 ? w.z : w.w));
+}
+
+// ------------------------------------------------------------------ shuffles
+template <int W>
+DK_INLINE float shfl(float v, int src) { return __shfl(v, src, W); }
+template <int W>
+DK_INLINE int shfl(int v, int src) { return __shfl(v, src, W); }
+template <int W>
+DK_INLINE float group_sum(float v) {
+#pragma unroll
+  for (int m = W / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, W);
+  return v;  // identical on every lane (each step adds two commuted operands)
+}
+
+// ------------------------------------------------------------------ terms
+// Pair word: i | j << 8 | type_i << 16 | type_j << 20 | flags << 24, plus the
+// radius sum as a float in the second word.  flags bit0 donor/acceptor pair,
+// bit1 both hydrophobic.
+struct PairRec {
+  uint32_t w;
+  float rsum;
+};
+
+// Weighted TRIDS terms (Methods: E_long, E_clash, E_Hbond) at distance d
+// (d2 = d*d): energy and dE/dd.
+DK_INLINE void trids_pair(float d2, float d, float rsum, uint32_t flags, const float* w, float& e,
+                          float& de) {
+  e = 0.f;
+  de = 0.f;
+  if (d2 < 100.0f) {
+    const float s = d - rsum - 3.0f;
+    const float ex = expf(-0.25f * s * s);
+    e -= w[0] * ex;
+    de += w[0] * 0.5f * s * ex;
+  }
+  const bool hb = flags & 1u;
+  const float dc = hb ? 2.6f : rsum;
+  if (d2 < dc * dc) {
+    const float dd = fmaxf(d, 0.1f);
+    e -= w[1] * logf(dd / dc);
+    if (d > 0.1f) de -= w[1] / dd;
+  }
+  if (hb && d2 < 3.4f * 3.4f) {
+    const float t = d - 2.88f;
+    const float ex = expf(-t * t * (1.0f / 0.18f));
+    e -= w[2] * ex;
+    de += w[2] * ex * t * (2.0f / 0.18f);
+  }
+}
+
+// Weighted Vina-form terms (gauss1, gauss2, repulsion, hydrophobic, hbond).
+DK_INLINE void vina_pair(float d2, float d, float rsum, uint32_t flags, const float* w, float& e,
+                         float& de) {
+  e = 0.f;
+  de = 0.f;
+  if (!(d2 < 64.0f)) return;
+  const float s = d - rsum;
+  const float g1 = expf(-4.0f * s * s);
+  e += w[0] * g1;
+  de -= w[0] * 8.0f * s * g1;
+  const float t = s - 3.0f;
+  const float g2 = expf(-0.25f * t * t);
+  e += w[1] * g2;
+  de -= w[1] * 0.5f * t * g2;
+  if (s < 0.f) {
+    e += w[2] * s * s;
+    de += w[2] * 2.0f * s;
+  }
+  if (flags & 2u) {
+    if (s < 0.5f) {
+      e += w[3];
+    } else if (s < 1.5f) {
+      e += w[3] * (1.5f - s);
+      de -= w[3];
+    }
+  }
+  if (flags & 1u) {
+    if (s < -0.7f) {
+      e += w[4];
+    } else if (s < 0.f) {
+      e -= w[4] * s * (1.0f / 0.7f);
+      de -= w[4] * (1.0f / 0.7f);
+    }
+  }
+}
+
+// Per-term values (no weights) of a receptor/ligand type pair for the map
+// build: each term's inside-cutoff decision is taken on the FP32 squared
+// distance d2; the values are evaluated in FP64 from the FP64 distance d.
+DK_INLINE void pair_terms_unweighted(int preset, float d2, double d, double rsum, float dclash2,
+                                     double dclash, uint32_t flags, double* v) {
+  if (preset == DOCK_PRESET_TRIDS) {
+    v[0] = v[1] = v[2] = 0.0;
+    if (d2 < 100.0f) {
+      const double s = d - rsum - 3.0;
+      v[0] = -exp(-0.25 * s * s);
+    }
+    if (d2 < dclash2) v[1] = -log(fmax(d, 0.1) / dclash);
+    if ((flags & 1u) && d2 < 3.4f * 3.4f) {
+      const double t = d - 2.88;
+      v[2] = -exp(-t * t / 0.18);
+    }
+  } else {
+    v[0] = v[1] = v[2] = v[3] = v[4] = 0.0;
+    if (!(d2 < 64.0f)) return;
+    const double s = d - rsum;
+    v[0] = exp(-4.0 * s * s);
+    const double t = s - 3.0;
+    v[1] = exp(-0.25 * t * t);
+    v[2] = s < 0.0 ? s * s : 0.0;
+    if (flags & 2u) v[3] = s < 0.5 ? 1.0 : (s < 1.5 ? 1.5 - s : 0.0);
+    if (flags & 1u) v[4] = s < -0.7 ? 1.0 : (s < 0.0 ? -s / 0.7 : 0.0);
+  }
+}
+
+// ------------------------------------------------------------------ trilinear
+// Cell = floor((p - o) / h) clamped to [0, n-2] at the clamped point; value,
+// analytic cell-local gradient, and the out-of-box penalty 10 |p - clamp(p)|_1.
+struct Trilerp {
+  float v, gx, gy, gz, eout;
+  int base;          // flat index of corner (0,0,0)
+  float fx, fy, fz;  // cell fractions
+};
+
+DK_INLINE void cell_axis(float p, float o, float hi, float inv_h, int n, float& pc, bool& in, int& c,
+                         float& f) {
+  pc = fminf(fmaxf(p, o), hi);
+  in = (p >= o) && (p <= hi);
+  const float u = (pc - o) * inv_h;
+  c = min(max(int(floorf(u)), 0), n - 2);
+  f = u - float(c);
+}
+
+DK_INLINE Trilerp trilerp(const float* __restrict__ M, const GridDev& g, float px, float py, float pz) {
+  Trilerp t;
+  float pcx, pcy, pcz;
+  bool ix, iy, iz;
+  int cx, cy, cz;
+  cell_axis(px, g.origin[0], g.hi[0], g.inv_spacing, g.dims[0], pcx, ix, cx, t.fx);
+  cell_axis(py, g.origin[1], g.hi[1], g.inv_spacing, g.dims[1], pcy, iy, cy, t.fy);
+  cell_axis(pz, g.origin[2], g.hi[2], g.inv_spacing, g.dims[2], pcz, iz, cz, t.fz);
+  const int nx = g.dims[0], nxy = g.dims[0] * g.dims[1];
+  t.base = (cz * g.dims[1] + cy) * nx + cx;
+  const float* p0 = M + t.base;
+  const float c000 = p0[0], c100 = p0[1], c010 = p0[nx], c110 = p0[nx + 1];
+  const float c001 = p0[nxy], c101 = p0[nxy + 1], c011 = p0[nxy + nx], c111 = p0[nxy + nx + 1];
+  const float fx = t.fx, fy = t.fy, fz = t.fz;
+  // interpolate along x, then y, then z
+  const float x00 = c000 + fx * (c100 - c000), x10 = c010 + fx * (c110 - c010);
+  const float x01 = c001 + fx * (c101 - c001), x11 = c011 + fx * (c111 - c011);
+  const float y0 = x00 + fy * (x10 - x00), y1 = x01 + fy * (x11 - x01);
+  t.v = y0 + fz * (y1 - y0);
+  const float dx00 = c100 - c000, dx10 = c110 - c010, dx01 = c101 - c001, dx11 = c111 - c011;
+  const float dxy0 = dx00 + fy * (dx10 - dx00), dxy1 = dx01 + fy * (dx11 - dx01);
+  const float gxf = dxy0 + fz * (dxy1 - dxy0);
+  const float gyf = (x10 - x00) + fz * ((x11 - x01) - (x10 - x00));
+  const float gzf = y1 - y0;
+  t.gx = ix ? gxf * g.inv_spacing : 0.f;
+  t.gy = iy ? gyf * g.inv_spacing : 0.f;
+  t.gz = iz ? gzf * g.inv_spacing : 0.f;
+  const float ox = px - pcx, oy = py - pcy, oz = pz - pcz;
+  t.eout = kOutK * (fabsf(ox) + fabsf(oy) + fabsf(oz));
+  t.gx += ox > 0.f ? kOutK : (ox < 0.f ? -kOutK : 0.f);
+  t.gy += oy > 0.f ? kOutK : (oy < 0.f ? -kOutK : 0.f);
+  t.gz += oz > 0.f ? kOutK : (oz < 0.f ? -kOutK : 0.f);
+  return t;
+}
+
+// ------------------------------------------------------------------ pose evaluation
+// Static per-ligand data held in registers by each lane of a group.
+template <int APL>
+struct LaneLig {
+  int n_atoms, n_frags, n_dof, n_pairs, fk_rounds, preset;
+  float c0x, c0y, c0z;
+  // atoms owned by this lane
+  float ax[APL], ay[APL], az[APL];
+  int atype[APL], afrag[APL], aorig[APL];
+  // fragment owned by this lane
+  float fu[3], fxb[3];
+  int fparent, fdof;
+  // DOF owned by this lane: range and, for torsions, the chain-rule record
+  float lo, hi;
+  int tsb, tse, ta, tb;
+  float w[kMaxTerms];
+};
+
+template <int LPP, int APL>
+DK_INLINE void load_lane_lig(LaneLig<APL>& L, const LigDev& lg, const float4* __restrict__ atoms,
+                             const FragDev* __restrict__ frags, const TorsDev* __restrict__ tors,
+                             const PocketDev& pk, int r) {
+  L.n_atoms = lg.n_atoms;
+  L.n_frags = lg.n_frags;
+  L.n_dof = lg.n_dof;
+  L.n_pairs = lg.n_pairs;
+  L.fk_rounds = lg.fk_rounds;
+  L.preset = pk.preset;
+  L.c0x = lg.c0[0];
+  L.c0y = lg.c0[1];
+  L.c0z = lg.c0[2];
+#pragma unroll
+  for (int s = 0; s < APL; ++s) {
+    const int a = APL * r + s;
+    if (a < lg.n_atoms) {
+      const float4 v = atoms[lg.atom_off + a];
+      const int bits = __float_as_int(v.w);
+      L.ax[s] = v.x;
+      L.ay[s] = v.y;
+      L.az[s] = v.z;
+      L.atype[s] = bits & 0xff;
+      L.afrag[s] = (bits >> 8) & 0xff;
+      L.aorig[s] = (bits >> 16) & 0xff;
+    } else {
+      L.ax[s] = L.ay[s] = L.az[s] = 0.f;
+      L.atype[s] = 0;
+      L.afrag[s] = 0;
+      L.aorig[s] = 0;
+    }
+  }
+  if (r < lg.n_frags) {
+    const FragDev f = frags[lg.frag_off + r];
+    L.fu[0] = f.u[0]; L.fu[1] = f.u[1]; L.fu[2] = f.u[2];
+    L.fxb[0] = f.xb[0]; L.fxb[1] = f.xb[1]; L.fxb[2] = f.xb[2];
+    L.fparent = f.parent;
+    L.fdof = f.dof;
+  } else {
+    L.fu[0] = L.fu[1] = L.fu[2] = 0.f;
+    L.fxb[0] = L.fxb[1] = L.fxb[2] = 0.f;
+    L.fparent = -1;
+    L.fdof = -1;
+  }
+  L.tsb = L.tse = L.ta = L.tb = 0;
+  if (r < 3) {
+    L.lo = lg.box_min[r];
+    L.hi = lg.box_max[r];
+  } else {
+    L.lo = -kPi;
+    L.hi = kPi;
+  }
+  if (r >= 6 && r < lg.n_dof) {
+    const TorsDev t = tors[lg.tors_off + r - 6];
+    L.tsb = t.sub_begin;
+    L.tse = t.sub_end;
+    L.ta = t.a;
+    L.tb = t.b;
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxTerms; ++k) L.w[k] = k < pk.n_terms ? pk.w[k] : 0.f;
+}
+
+// Per-group LDS slab: coordinates (w = type bits) and intra-pair forces.
+struct GroupSlab {
+  float4* xs;  // [LPP*APL]
+  float* fx;   // [LPP*APL]
+  float* fy;
+  float* fz;
+};
+
+struct EvalOut {
+  float E;      // total energy (same on every lane of the group)
+  float g;      // dE/dq for this lane's DOF (0 beyond n_dof)
+};
+
+// Rigid-body part of a pose, shared by every lane of the group.
+struct Rigid {
+  float Tx, Ty, Tz, sa, ca, sb, cb;
+};
+
+// Forward kinematics: world coordinates of the atoms owned by lane r.
+// Fragment transforms are composed root-to-leaf by pointer jumping
+// (ceil(log2) rounds of "compose with my current ancestor's transform").
+template <int LPP, int APL>
+DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][3]) {
+  // ---- rigid DOFs to every lane
+  const float Tx = shfl<LPP>(q, 0), Ty = shfl<LPP>(q, 1), Tz = shfl<LPP>(q, 2);
+  const float al = shfl<LPP>(q, 3), be = shfl<LPP>(q, 4), ga = shfl<LPP>(q, 5);
+  float sa, ca, sb, cb, sg, cg;
+  sincosf(al, &sa, &ca);
+  sincosf(be, &sb, &cb);
+  sincosf(ga, &sg, &cg);
+  // ---- fragment transforms: lane f starts from its own local transform
+  const float th = shfl<LPP>(q, L.fdof >= 0 ? L.fdof : 0);
+  float m[9], t[3];
+  int anc = L.fparent;
+  if (L.fparent < 0) {
+    // root (and idle lanes): world rotation R = Rz Ry Rx, t = T - R c0
+    m[0] = ca * cb; m[1] = ca * sb * sg - sa * cg; m[2] = ca * sb * cg + sa * sg;
+    m[3] = sa * cb; m[4] = sa * sb * sg + ca * cg; m[5] = sa * sb * cg - ca * sg;
+    m[6] = -sb;     m[7] = cb * sg;                m[8] = cb * cg;
+    t[0] = Tx - (m[0] * L.c0x + m[1] * L.c0y + m[2] * L.c0z);
+    t[1] = Ty - (m[3] * L.c0x + m[4] * L.c0y + m[5] * L.c0z);
+    t[2] = Tz - (m[6] * L.c0x + m[7] * L.c0y + m[8] * L.c0z);
+  } else {
+    // Rodrigues rotation about u through xb by theta: y -> B y + (xb - B xb)
+    float st, ct;
+    sincosf(th, &st, &ct);
+    const float ux = L.fu[0], uy = L.fu[1], uz = L.fu[2], oc = 1.f - ct;
+    m[0] = ct + ux * ux * oc;      m[1] = ux * uy * oc - uz * st; m[2] = ux * uz * oc + uy * st;
+    m[3] = uy * ux * oc + uz * st; m[4] = ct + uy * uy * oc;      m[5] = uy * uz * oc - ux * st;
+    m[6] = uz * ux * oc - uy * st; m[7] = uz * uy * oc + ux * st; m[8] = ct + uz * uz * oc;
+    t[0] = L.fxb[0] - (m[0] * L.fxb[0] + m[1] * L.fxb[1] + m[2] * L.fxb[2]);
+    t[1] = L.fxb[1] - (m[3] * L.fxb[0] + m[4] * L.fxb[1] + m[5] * L.fxb[2]);
+    t[2] = L.fxb[2] - (m[6] * L.fxb[0] + m[7] * L.fxb[1] + m[8] * L.fxb[2]);
+  }
+  // pointer jumping: C_f <- C_anc o C_f until every fragment reaches the root
+  for (int it = 0; it < L.fk_rounds; ++it) {
+    const int src = anc >= 0 ? anc : r;
+    float a[9], b[3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = shfl<LPP>(m[k], src);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) b[k] = shfl<LPP>(t[k], src);
+    const int anc2 = shfl<LPP>(anc, src);
+    if (anc >= 0) {
+      float nm[9], nt[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          nm[3 * i + j] = a[3 * i] * m[j] + a[3 * i + 1] * m[3 + j] + a[3 * i + 2] * m[6 + j];
+        nt[i] = a[3 * i] * t[0] + a[3 * i + 1] * t[1] + a[3 * i + 2] * t[2] + b[i];
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) m[k] = nm[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t[k] = nt[k];
+      anc = anc2;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < APL; ++s) {
+    const int f = L.afrag[s];
+    float a[9], b[3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = shfl<LPP>(m[k], f);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) b[k] = shfl<LPP>(t[k], f);
+    x[s][0] = a[0] * L.ax[s] + a[1] * L.ay[s] + a[2] * L.az[s] + b[0];
+    x[s][1] = a[3] * L.ax[s] + a[4] * L.ay[s] + a[5] * L.az[s] + b[1];
+    x[s][2] = a[6] * L.ax[s] + a[7] * L.ay[s] + a[8] * L.az[s] + b[2];
+  }
+  Rigid rg;
+  rg.Tx = Tx; rg.Ty = Ty; rg.Tz = Tz;
+  rg.sa = sa; rg.ca = ca; rg.sb = sb; rg.cb = cb;
+  return rg;
+}
+
+// One evaluation of E and dE/dq at the pose whose DOF r is held by lane r.
+// Optionally leaves world coordinates and atom gradients in xo/go.
+template <int LPP, int APL, bool WANT_X = false>
+DK_INLINE EvalOut eval_pose(const LaneLig<APL>& L, float q, const float* __restrict__ M,
+                            const GridDev& grid, const PairRec* __restrict__ pairs,
+                            const GroupSlab& S, int r, float (*xo)[3] = nullptr,
+                            float (*go)[3] = nullptr) {
+  // ---- atoms: place, interpolate, publish coordinates to the slab
+  float x[APL][3], g[APL][3];
+  const Rigid rg = fk_place<LPP, APL>(L, q, r, x);
+  const float Tx = rg.Tx, Ty = rg.Ty, Tz = rg.Tz;
+  const float sa = rg.sa, ca = rg.ca, sb = rg.sb, cb = rg.cb;
+  float e_lane = 0.f;
+#pragma unroll
+  for (int s = 0; s < APL; ++s) {
+    const int atom = APL * r + s;
+    if (atom < L.n_atoms) {
+      const size_t nxyz = size_t(grid.dims[0]) * grid.dims[1] * grid.dims[2];
+      const Trilerp tl = trilerp(M + size_t(L.atype[s]) * nxyz, grid, x[s][0], x[s][1], x[s][2]);
+      e_lane += tl.v + tl.eout;
+      g[s][0] = tl.gx;
+      g[s][1] = tl.gy;
+      g[s][2] = tl.gz;
+      S.xs[atom] = make_float4(x[s][0], x[s][1], x[s][2], 0.f);
+      S.fx[atom] = 0.f;
+      S.fy[atom] = 0.f;
+      S.fz[atom] = 0.f;
+    } else {
+      g[s][0] = g[s][1] = g[s][2] = 0.f;
+    }
+  }
+  wave_sync();
+  // ---- intra-ligand pairs, strided over the group's lanes
+  for (int p = r; p < L.n_pairs; p += LPP) {
+    const PairRec pr = pairs[p];
+    const int i = pr.w & 0xff, j = (pr.w >> 8) & 0xff;
+    const uint32_t flags = pr.w >> 24;
+    const float4 xi = S.xs[i], xj = S.xs[j];
+    const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+    const float d2 = dx * dx + dy * dy + dz * dz;
+    const float d = sqrtf(d2);
+    float e, de;
+    if (L.preset == DOCK_PRESET_TRIDS)
+      trids_pair(d2, d, pr.rsum, flags, L.w, e, de);
+    else
+      vina_pair(d2, d, pr.rsum, flags, L.w, e, de);
+    e_lane += e;
+    if (de != 0.f && d > 0.f) {
+      const float c = de / d;
+      const float fx = c * dx, fy = c * dy, fz = c * dz;
+      atomicAdd(&S.fx[i], fx);
+      atomicAdd(&S.fy[i], fy);
+      atomicAdd(&S.fz[i], fz);
+      atomicAdd(&S.fx[j], -fx);
+      atomicAdd(&S.fy[j], -fy);
+      atomicAdd(&S.fz[j], -fz);
+    }
+  }
+  wave_sync();
+  // ---- per-atom total gradient, torque terms and their prefix sums
+  float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float vs[APL][6];
+#pragma unroll
+  for (int s = 0; s < APL; ++s) {
+    const int atom = APL * r + s;
+    if (atom < L.n_atoms) {
+      g[s][0] += S.fx[atom];
+      g[s][1] += S.fy[atom];
+      g[s][2] += S.fz[atom];
+    }
+    const float rx = x[s][0] - Tx, ry = x[s][1] - Ty, rz = x[s][2] - Tz;
+    vs[s][0] = g[s][0];
+    vs[s][1] = g[s][1];
+    vs[s][2] = g[s][2];
+    vs[s][3] = ry * g[s][2] - rz * g[s][1];
+    vs[s][4] = rz * g[s][0] - rx * g[s][2];
+    vs[s][5] = rx * g[s][1] - ry * g[s][0];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] += vs[s][k];
+    if (WANT_X) {
+      xo[s][0] = x[s][0]; xo[s][1] = x[s][1]; xo[s][2] = x[s][2];
+      go[s][0] = g[s][0]; go[s][1] = g[s][1]; go[s][2] = g[s][2];
+    }
+  }
+  // inclusive scan over lanes (lane r covers atoms up to APL*r + APL - 1)
+#pragma unroll
+  for (int off = 1; off < LPP; off <<= 1) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float o = __shfl_up(v[k], off, LPP);
+      if (r >= off) v[k] += o;
+    }
+  }
+  // prefix at an atom boundary: P(end) = sum of atoms [0, end)
+  // lane holding atoms [APL*l, APL*l+APL): inclusive value v; with APL = 2,
+  // the partial up to its first atom is v - vs[1].
+  float vlast[6];
+  float vfirst[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    vlast[k] = v[k];
+    vfirst[k] = APL == 2 ? v[k] - vs[APL - 1][k] : v[k];
+  }
+  auto prefix = [&](int end, float* out) {
+    // all lanes call this with their own `end`; returns sum over [0, end)
+    const int a = end - 1;
+    const int l = a >= 0 ? a / APL : 0;
+    const bool first = APL == 2 && (a % APL) == 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float lv = shfl<LPP>(vlast[k], l);
+      const float fv = shfl<LPP>(vfirst[k], l);
+      out[k] = a < 0 ? 0.f : (first ? fv : lv);
+    }
+  };
+  float tot[6];
+  prefix(L.n_atoms, tot);
+  float pb[6], pe[6];
+  prefix(L.tsb, pb);
+  prefix(L.tse, pe);
+  // axis atoms of this lane's torsion
+  const float4 xa = S.xs[L.ta], xb = S.xs[L.tb];
+  // ---- energy
+  EvalOut out;
+  out.E = group_sum<LPP>(e_lane);
+  // ---- gradient of this lane's DOF
+  float gq = 0.f;
+  if (r < 3) {
+    gq = tot[r];
+  } else if (r == 3) {
+    gq = tot[5];
+  } else if (r == 4) {
+    gq = -sa * tot[3] + ca * tot[4];
+  } else if (r == 5) {
+    gq = ca * cb * tot[3] + sa * cb * tot[4] - sb * tot[5];
+  } else if (r < L.n_dof) {
+    float Sg[3], St[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Sg[k] = pe[k] - pb[k];
+      St[k] = pe[3 + k] - pb[3 + k];
+    }
+    float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
+    const float inv = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+    ux *= inv; uy *= inv; uz *= inv;
+    const float bx = xb.x - Tx, by = xb.y - Ty, bz = xb.z - Tz;
+    // sum_sub (x_i - x_b) x g_i = St - r_b x Sg
+    const float cx = St[0] - (by * Sg[2] - bz * Sg[1]);
+    const float cy = St[1] - (bz * Sg[0] - bx * Sg[2]);
+    const float cz = St[2] - (bx * Sg[1] - by * Sg[0]);
+    gq = ux * cx + uy * cy + uz * cz;
+  }
+  out.g = gq;
+  wave_sync();  // slab reuse by the next evaluation
+  return out;
+}
+
+DK_INLINE float wrap_angle(float a) { return a - kTwoPi * floorf((a + kPi) * kInvTwoPi); }
+
+}  // namespace dock

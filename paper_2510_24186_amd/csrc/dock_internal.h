@@ -1,0 +1,104 @@
+// Internal layout shared by the host half (ligand preparation, planning,
+// ABI) and the device half (HIP kernels) of libdock.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/dock.h"
+
+namespace dock {
+
+constexpr int kTypes = DOCK_N_TYPES;
+constexpr int kMaxAtoms = DOCK_MAX_ATOMS;
+constexpr int kMaxTors = DOCK_MAX_TORS;
+constexpr int kMaxDof = 6 + DOCK_MAX_TORS;
+constexpr int kMaxTerms = DOCK_MAX_TERMS;
+
+// Per-ligand record, device resident.  Atoms are stored in fragment
+// depth-first pre-order so that every torsion's moving subtree is one
+// contiguous atom range (the chain rule sums over ranges).
+struct alignas(16) LigDev {
+  int n_atoms, n_tors, n_frags, n_pairs;
+  int atom_off, pair_off, frag_off, tors_off;
+  int pocket, fk_rounds, n_dof, pad0;
+  float c0[3];
+  float box_min[3];
+  float box_max[3];
+  float pad1[3];
+};
+
+// Fragment record (DFS numbering).  Root: parent = -1, dof = -1.
+// A child turns about the input-frame axis through xb with unit direction u.
+struct alignas(16) FragDev {
+  float u[3];
+  float xb[3];
+  int parent;
+  int dof;
+};
+
+// Torsion record, indexed by torsion k (DOF 6 + k): its moving atoms are the
+// DFS range [sub_begin, sub_end); a, b are the axis atoms (DFS numbering).
+struct alignas(16) TorsDev {
+  int sub_begin, sub_end, a, b;
+};
+
+// Term constants for one (type_i, type_j) pair.  The FP32 copies decide
+// cutoffs and serve the FP32 pair terms; the FP64 copies serve the map build.
+struct alignas(16) TypePair {
+  float rsum;     // R_i + R_j, rounded once from FP64
+  float dclash;   // d_clash (2.6 for donor/acceptor pairs, else rsum)
+  float dclash2;  // fl32(dclash)^2 in FP32
+  uint32_t flags; // bit0 donor/acceptor pair, bit1 both hydrophobic
+  double rsum64;
+  double dclash64;
+};
+
+// Grid geometry of one pocket.
+struct GridDev {
+  float origin[3];
+  float spacing, inv_spacing;
+  int dims[3];
+  float hi[3];
+};
+
+struct PocketDev {
+  GridDev grid;
+  const float* M;   // combined maps [8][nz][ny][nx]
+  const float* G;   // per-term maps [8][K][nz][ny][nx] (may be null)
+  int preset, n_terms;
+  float w[kMaxTerms];
+};
+
+// ---------------------------------------------------------------- host side
+
+struct LigandHost {
+  int n_atoms = 0, n_tors = 0, n_frags = 0, root = 0, height = 0, pocket = 0;
+  double c0[3] = {0, 0, 0};
+  float box_min[3] = {0, 0, 0}, box_max[3] = {0, 0, 0};
+  std::vector<float> x0;               // [N*3] input coordinates (caller order)
+  std::vector<uint8_t> type;           // caller order
+  std::vector<int> atom_frag;          // caller order, fragment ids by lowest atom
+  std::vector<int> frag_parent;        // [F]
+  std::vector<int> bfs;                // [F]
+  std::vector<int> tors_frag, tors_a, tors_b;  // [n_t]
+  std::vector<int> pair_i, pair_j;     // caller order, lexicographic
+  // packing (DFS order)
+  std::vector<int> dfs_atom;           // new atom index -> caller atom index
+  std::vector<int> atom_new;           // caller atom index -> new index
+  std::vector<int> dfs_frag;           // new fragment id -> caller fragment id
+  std::vector<int> frag_new;           // caller fragment id -> new id
+};
+
+// Builds the topology of one ligand; returns DOCK_OK or an error code with
+// a message in `err`.
+int prepare_ligand(int n, const uint8_t* element, const uint8_t* n_h, const float* xyz,
+                   int n_bonds, const int32_t* bonds, const uint8_t* rotatable,
+                   const float* box_min, const float* box_max, LigandHost& out, std::string& err);
+
+void type_pair_table(int preset, TypePair table[kTypes * kTypes]);
+void preset_weights(int preset, float* w, int* K);
+
+}  // namespace dock

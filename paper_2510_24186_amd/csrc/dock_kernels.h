@@ -1,0 +1,99 @@
+// Kernel argument blocks and launchers (host <-> device interface of libdock).
+#pragma once
+
+#include "dock_internal.h"
+
+namespace dock {
+
+struct PairRec;
+
+struct LigandArrays {
+  const LigDev* ligs;
+  const float4* atoms;   // DFS order; w = bits(type | frag << 8 | caller index << 16)
+  const FragDev* frags;
+  const TorsDev* tors;
+  const PairRec* pairs;
+};
+
+struct ScoreArgs {
+  LigandArrays L;
+  const PocketDev* pockets;
+  int n_ligands, n_pockets;
+  long long n_poses;
+  const int* pose_lig;
+  const float* q;
+  int q_stride;
+  float* E;
+  float* dEdq;
+  float* xyz;
+  int xyz_stride;
+  int max_pairs;
+};
+
+struct SampleArgs {
+  LigandArrays L;
+  const PocketDev* pockets;
+  const int2* items;      // (ligand, first trajectory)
+  int n_items;
+  int* queue;             // persistent work counter, or null: item = blockIdx.x
+  const int* step_base;   // device: MC steps already taken
+  int step_off;           // this launch covers steps base+off+1 .. base+off+count
+  int step_count;
+  int init;               // draw initial poses and score them instead of stepping
+  int n_traj, q_stride;
+  int n_local, local_opt;
+  float lr, b1, b2, eps, mc_beta;
+  unsigned seed;
+  float* q_cur;
+  float* E_cur;
+  float* q_best;
+  float* E_best;
+  int* n_evals;
+  float* trace;
+  int trace_cap;
+  int max_pairs;
+};
+
+struct BestArgs {
+  LigandArrays L;
+  int n_ligands, n_traj, q_stride;
+  const float* E_best;
+  const float* q_best;
+  int top_n;
+  float rmsd_cut, w_tor;
+  float* E_out;
+  float* E_screen;
+  float* q_out;
+  int* idx_out;
+  float* xyz_out;
+  int xyz_stride;
+  int* n_out;
+  int t_pad;
+};
+
+struct MapArgs {
+  const float4* rec;  // xyz, w = bits(type)
+  int n_rec;
+  GridDev grid;
+  int preset, n_terms;
+  float w[kMaxTerms];
+  TypePair tab[kTypes * kTypes];
+  float* G;  // [8][K][nodes] or null
+  float* M;  // [8][nodes]
+};
+
+// LDS bytes a sampler block of `block` threads needs.
+size_t sample_lds_bytes(int lpp, int apl, int block, int max_pairs);
+size_t score_lds_bytes(int lpp, int apl, int max_pairs);
+
+hipError_t launch_map_build(const MapArgs& a, hipStream_t s);
+hipError_t launch_score(const ScoreArgs& a, int lpp, int apl, hipStream_t s);
+hipError_t launch_sample(const SampleArgs& a, int lpp, int apl, int grid, int block, hipStream_t s);
+hipError_t launch_best(const BestArgs& a, hipStream_t s);
+hipError_t launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, long long n, uint32_t* out,
+                         hipStream_t s);
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
+hipError_t launch_add_int(int* p, int v, hipStream_t s);
+int sample_max_blocks_per_cu(int lpp, int apl, int block, size_t lds);
+
+}  // namespace dock

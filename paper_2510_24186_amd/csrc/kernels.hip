@@ -1,0 +1,512 @@
+// HIP kernels of the docking hot path for gfx950 and their launchers.
+//
+//  map_kernel     receptor grid maps (one thread per node, receptor atoms
+//                 staged through LDS, terms and sums in FP64)
+//  score_kernel   E and dE/dq of caller-supplied poses
+//  sample_kernel  Metropolis MC + local refinement; one LPP-lane group per
+//                 trajectory, trajectory state in registers for a whole
+//                 chunk of MC steps; plain (one launch per ligand) or
+//                 persistent (device work queue over ragged-packed items)
+//  best_kernel    per ligand: bitonic sort of the trajectories' best
+//                 energies, greedy RMSD clustering, top N
+#include <float.h>
+#include <math.h>
+
+#include "dock_device.h"
+#include "dock_kernels.h"
+
+namespace dock {
+
+// ================================================================ maps
+
+template <int K>
+__global__ void __launch_bounds__(256) map_kernel(MapArgs a) {
+  __shared__ float4 tile[256];
+  __shared__ TypePair stab[kTypes * kTypes];
+  if (threadIdx.x < kTypes * kTypes) stab[threadIdx.x] = a.tab[threadIdx.x];
+  const int nx = a.grid.dims[0], ny = a.grid.dims[1], nz = a.grid.dims[2];
+  const long long total = (long long)nx * ny * nz;
+  const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool live = node < total;
+  const int ix = int(node % nx), iy = int((node / nx) % ny), iz = int(node / ((long long)nx * ny));
+  // node coordinate: FP64 origin + spacing * index, rounded once to FP32
+  const float px = float(double(a.grid.origin[0]) + double(a.grid.spacing) * ix);
+  const float py = float(double(a.grid.origin[1]) + double(a.grid.spacing) * iy);
+  const float pz = float(double(a.grid.origin[2]) + double(a.grid.spacing) * iz);
+  const float cmax2 = a.preset == DOCK_PRESET_TRIDS ? 100.0f : 64.0f;
+  double acc[kTypes][K];
+#pragma unroll
+  for (int t = 0; t < kTypes; ++t)
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[t][k] = 0.0;
+  for (int base = 0; base < a.n_rec; base += 256) {
+    __syncthreads();
+    if (base + threadIdx.x < a.n_rec) tile[threadIdx.x] = a.rec[base + threadIdx.x];
+    __syncthreads();
+    const int cnt = min(256, a.n_rec - base);
+    if (!live) continue;
+    for (int j = 0; j < cnt; ++j) {
+      const float4 rj = tile[j];
+      // FP32 squared distance in a fixed order, no contraction: the
+      // inside-cutoff decisions depend on these exact bits.
+      const float dx = __fsub_rn(px, rj.x), dy = __fsub_rn(py, rj.y), dz = __fsub_rn(pz, rj.z);
+      const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+      if (!(d2 < cmax2)) continue;
+      const double ex = double(px) - double(rj.x), ey = double(py) - double(rj.y),
+                   ez = double(pz) - double(rj.z);
+      const double d = sqrt(ex * ex + ey * ey + ez * ez);
+      const int tr = __float_as_int(rj.w) & 0xff;
+#pragma unroll
+      for (int t = 0; t < kTypes; ++t) {
+        const TypePair tp = stab[t * kTypes + tr];
+        double v[kMaxTerms];
+        pair_terms_unweighted(a.preset, d2, d, tp.rsum64, tp.dclash2, tp.dclash64, tp.flags, v);
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[t][k] += v[k];
+      }
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int t = 0; t < kTypes; ++t) {
+    double m = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      m += double(a.w[k]) * acc[t][k];
+      if (a.G) a.G[((long long)t * K + k) * total + node] = float(acc[t][k]);
+    }
+    a.M[(long long)t * total + node] = float(m);
+  }
+}
+
+hipError_t launch_map_build(const MapArgs& a, hipStream_t s) {
+  const long long total = (long long)a.grid.dims[0] * a.grid.dims[1] * a.grid.dims[2];
+  const unsigned blocks = unsigned((total + 255) / 256);
+  if (a.n_terms == 3)
+    hipLaunchKernelGGL(map_kernel<3>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(map_kernel<5>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ================================================================ slabs
+
+template <int LPP, int APL>
+DK_INLINE GroupSlab make_slab(unsigned char* base) {
+  constexpr int NA = LPP * APL;
+  GroupSlab S;
+  S.xs = reinterpret_cast<float4*>(base);
+  S.fx = reinterpret_cast<float*>(base + 16 * NA);
+  S.fy = S.fx + NA;
+  S.fz = S.fy + NA;
+  return S;
+}
+constexpr size_t slab_bytes(int lpp, int apl) { return size_t(lpp) * apl * 28; }
+// pair records padded to 16 bytes so the float4 slab that follows is aligned
+constexpr size_t pair_bytes(int max_pairs) { return (size_t(max_pairs) * 8 + 15) / 16 * 16; }
+
+size_t score_lds_bytes(int lpp, int apl, int max_pairs) {
+  const int gpb = 64 / lpp;
+  return size_t(gpb) * (pair_bytes(max_pairs) + slab_bytes(lpp, apl));
+}
+
+size_t sample_lds_bytes(int lpp, int apl, int block, int max_pairs) {
+  const int gpb = block / lpp;
+  return pair_bytes(max_pairs) + size_t(gpb) * slab_bytes(lpp, apl) + 16;
+}
+
+// ================================================================ score
+
+template <int LPP, int APL>
+__global__ void __launch_bounds__(64) score_kernel(ScoreArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int GPB = 64 / LPP;
+  const int grp = threadIdx.x / LPP, r = threadIdx.x % LPP;
+  const long long pose = (long long)blockIdx.x * GPB + grp;
+  unsigned char* mine = smem + size_t(grp) * (pair_bytes(a.max_pairs) + slab_bytes(LPP, APL));
+  PairRec* gp = reinterpret_cast<PairRec*>(mine);
+  const GroupSlab S = make_slab<LPP, APL>(mine + pair_bytes(a.max_pairs));
+  if (pose >= a.n_poses) return;
+  const int lig = a.pose_lig[pose];
+  if (lig < 0 || lig >= a.n_ligands) {
+    if (r == 0) a.E[pose] = __int_as_float(0x7fc00000);
+    return;
+  }
+  const LigDev lg = a.L.ligs[lig];
+  const PocketDev pk = a.pockets[lg.pocket];
+  LaneLig<APL> L;
+  load_lane_lig<LPP, APL>(L, lg, a.L.atoms, a.L.frags, a.L.tors, pk, r);
+  for (int p = r; p < lg.n_pairs; p += LPP) gp[p] = a.L.pairs[lg.pair_off + p];
+  wave_sync();
+  const float q = r < lg.n_dof ? a.q[pose * a.q_stride + r] : 0.f;
+  float xo[APL][3], go[APL][3];
+  const EvalOut o = eval_pose<LPP, APL, true>(L, q, pk.M, pk.grid, gp, S, r, xo, go);
+  if (r == 0) a.E[pose] = o.E;
+  if (a.dEdq && r < lg.n_dof) a.dEdq[pose * a.q_stride + r] = o.g;
+  if (a.xyz) {
+#pragma unroll
+    for (int s = 0; s < APL; ++s) {
+      const int atom = APL * r + s;
+      if (atom < lg.n_atoms) {
+        float* dst = a.xyz + pose * a.xyz_stride + 3 * L.aorig[s];
+        dst[0] = xo[s][0];
+        dst[1] = xo[s][1];
+        dst[2] = xo[s][2];
+      }
+    }
+  }
+}
+
+hipError_t launch_score(const ScoreArgs& a, int lpp, int apl, hipStream_t s) {
+  const int gpb = 64 / lpp;
+  const unsigned blocks = unsigned((a.n_poses + gpb - 1) / gpb);
+  const size_t lds = score_lds_bytes(lpp, apl, a.max_pairs);
+  if (blocks == 0) return hipSuccess;
+  if (lpp == 16 && apl == 1)
+    hipLaunchKernelGGL((score_kernel<16, 1>), dim3(blocks), dim3(64), lds, s, a);
+  else if (lpp == 32 && apl == 1)
+    hipLaunchKernelGGL((score_kernel<32, 1>), dim3(blocks), dim3(64), lds, s, a);
+  else if (lpp == 64 && apl == 1)
+    hipLaunchKernelGGL((score_kernel<64, 1>), dim3(blocks), dim3(64), lds, s, a);
+  else
+    hipLaunchKernelGGL((score_kernel<64, 2>), dim3(blocks), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+// ================================================================ sampler
+
+template <int APL>
+DK_INLINE float wrap_clamp(float q, int r, const LaneLig<APL>& L) {
+  if (r < 3) return fminf(fmaxf(q, L.lo), L.hi);
+  return wrap_angle(q);
+}
+
+template <int LPP, int APL>
+DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const float* M, const GridDev& grid,
+                        const PairRec* pairs, const GroupSlab& S, int lig, int traj, int r) {
+  const size_t ti = size_t(lig) * a.n_traj + traj;
+  const uint32_t k0 = uint32_t(lig), k1 = a.seed;
+  const bool dof = r < L.n_dof;
+  const int qs = a.q_stride;
+  int nev = a.n_evals[ti];
+  float* trow = a.trace ? a.trace + ti * size_t(a.trace_cap) * (2 * qs + 1) : nullptr;
+  auto record = [&](float qv, float gv, float Ev) {
+    if (trow && nev < a.trace_cap) {
+      float* row = trow + size_t(nev) * (2 * qs + 1);
+      if (r < qs) {
+        row[r] = dof ? qv : 0.f;
+        row[qs + r] = dof ? gv : 0.f;
+      }
+      if (r == 0) row[2 * qs] = Ev;
+    }
+    ++nev;
+  };
+  if (a.init) {
+    const uint4 w = philox4x32_10(make_uint4(uint32_t(traj), 0u, 0u, uint32_t(r >> 2)), k0, k1);
+    const float q = dof ? L.lo + (L.hi - L.lo) * u01(pick4(w, r & 3)) : 0.f;
+    const EvalOut o = eval_pose<LPP, APL>(L, q, M, grid, pairs, S, r);
+    record(q, o.g, o.E);
+    if (dof) {
+      a.q_cur[ti * qs + r] = q;
+      a.q_best[ti * qs + r] = q;
+    }
+    if (r == 0) {
+      a.E_cur[ti] = o.E;
+      a.E_best[ti] = o.E;
+      a.n_evals[ti] = nev;
+    }
+    return;
+  }
+  float q = dof ? a.q_cur[ti * qs + r] : 0.f;
+  float qb = dof ? a.q_best[ti * qs + r] : 0.f;
+  float Ecur = a.E_cur[ti], Ebest = a.E_best[ti];
+  const int base = *a.step_base + a.step_off;
+  for (int s = base + 1; s <= base + a.step_count; ++s) {
+    const uint4 w = philox4x32_10(make_uint4(uint32_t(traj), uint32_t(s), 1u, 0u), k0, k1);
+    const int j = int(__umulhi(w.x, uint32_t(L.n_dof)));
+    float qn = q;
+    if (r == j) qn = L.lo + (L.hi - L.lo) * u01(w.y);
+    float E;
+    if (a.local_opt == DOCK_LOCAL_ADAM) {
+      float m = 0.f, v = 0.f, b1t = 1.f, b2t = 1.f;
+      for (int t = 0; t < a.n_local; ++t) {
+        const EvalOut o = eval_pose<LPP, APL>(L, qn, M, grid, pairs, S, r);
+        record(qn, o.g, o.E);
+        m = a.b1 * m + (1.f - a.b1) * o.g;
+        v = a.b2 * v + (1.f - a.b2) * o.g * o.g;
+        b1t *= a.b1;
+        b2t *= a.b2;
+        const float mh = m / (1.f - b1t), vh = v / (1.f - b2t);
+        if (dof) qn = wrap_clamp(qn - a.lr * mh / (sqrtf(vh) + a.eps), r, L);
+      }
+      const EvalOut o = eval_pose<LPP, APL>(L, qn, M, grid, pairs, S, r);
+      record(qn, o.g, o.E);
+      E = o.E;
+    } else {
+      EvalOut o = eval_pose<LPP, APL>(L, qn, M, grid, pairs, S, r);
+      record(qn, o.g, o.E);
+      E = o.E;
+      float g = o.g;
+      for (int l = 0; l < a.n_local; ++l) {
+        const float gn = sqrtf(group_sum<LPP>(dof ? g * g : 0.f));
+        if (!(gn > 0.f)) break;
+        const float d = dof ? -g / gn : 0.f;
+        const float slope = -gn;
+        float alpha = 1.f;
+        bool ok = false;
+        for (int h = 0; h <= 10; ++h) {
+          const float qc = dof ? wrap_clamp(qn + alpha * d, r, L) : 0.f;
+          const EvalOut oc = eval_pose<LPP, APL>(L, qc, M, grid, pairs, S, r);
+          record(qc, oc.g, oc.E);
+          if (oc.E <= E + 1e-4f * alpha * slope) {
+            qn = qc;
+            E = oc.E;
+            g = oc.g;
+            ok = true;
+            break;
+          }
+          alpha *= 0.5f;
+        }
+        if (!ok) break;
+      }
+    }
+    const float u = u01(w.z);
+    const bool acc = u < expf(-a.mc_beta * (E - Ecur));
+    if (acc) {
+      q = qn;
+      Ecur = E;
+    }
+    if (E < Ebest) {
+      qb = qn;
+      Ebest = E;
+    }
+  }
+  if (dof) {
+    a.q_cur[ti * qs + r] = q;
+    a.q_best[ti * qs + r] = qb;
+  }
+  if (r == 0) {
+    a.E_cur[ti] = Ecur;
+    a.E_best[ti] = Ebest;
+    a.n_evals[ti] = nev;
+  }
+}
+
+template <int LPP, int APL, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) sample_kernel(SampleArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int GPB = BLOCK / LPP;
+  const int grp = threadIdx.x / LPP, r = threadIdx.x % LPP;
+  PairRec* sp = reinterpret_cast<PairRec*>(smem);
+  unsigned char* slabs = smem + pair_bytes(a.max_pairs);
+  const GroupSlab S = make_slab<LPP, APL>(slabs + size_t(grp) * slab_bytes(LPP, APL));
+  int* s_item = reinterpret_cast<int*>(slabs + size_t(GPB) * slab_bytes(LPP, APL));
+  int taken = 0;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int it;
+      if (a.queue)
+        it = atomicAdd(a.queue, 1);
+      else
+        it = taken == 0 ? int(blockIdx.x) : a.n_items;
+      *s_item = it;
+    }
+    __syncthreads();
+    const int item = *s_item;
+    __syncthreads();
+    if (item >= a.n_items) break;
+    ++taken;
+    const int2 wi = a.items[item];
+    const int lig = wi.x;
+    const LigDev lg = a.L.ligs[lig];
+    for (int p = threadIdx.x; p < lg.n_pairs; p += BLOCK) sp[p] = a.L.pairs[lg.pair_off + p];
+    __syncthreads();
+    const int traj = wi.y + grp;
+    if (traj < a.n_traj) {
+      const PocketDev pk = a.pockets[lg.pocket];
+      LaneLig<APL> L;
+      load_lane_lig<LPP, APL>(L, lg, a.L.atoms, a.L.frags, a.L.tors, pk, r);
+      run_traj<LPP, APL>(a, L, pk.M, pk.grid, sp, S, lig, traj, r);
+    }
+    __syncthreads();
+  }
+}
+
+template <int LPP, int APL, int BLOCK>
+static hipError_t launch_sample_t(const SampleArgs& a, int grid, hipStream_t s) {
+  const size_t lds = sample_lds_bytes(LPP, APL, BLOCK, a.max_pairs);
+  hipLaunchKernelGGL((sample_kernel<LPP, APL, BLOCK>), dim3(grid), dim3(BLOCK), lds, s, a);
+  return hipGetLastError();
+}
+
+#define DOCK_SAMPLE_CASES(X)                                                        \
+  X(16, 1, 64) X(32, 1, 64) X(64, 1, 64) X(64, 2, 64) X(16, 1, 128) X(32, 1, 128) \
+      X(64, 1, 128) X(64, 2, 128) X(16, 1, 256) X(32, 1, 256) X(64, 1, 256) X(64, 2, 256)
+
+hipError_t launch_sample(const SampleArgs& a, int lpp, int apl, int grid, int block, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+#define X(L, A, B) \
+  if (lpp == L && apl == A && block == B) return launch_sample_t<L, A, B>(a, grid, s);
+  DOCK_SAMPLE_CASES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+int sample_max_blocks_per_cu(int lpp, int apl, int block, size_t lds) {
+  int n = 0;
+#define X(L, A, B)                                                                           \
+  if (lpp == L && apl == A && block == B) {                                                  \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_kernel<L, A, B>, B, lds) != \
+        hipSuccess)                                                                          \
+      n = 1;                                                                                 \
+    return n > 0 ? n : 1;                                                                    \
+  }
+  DOCK_SAMPLE_CASES(X)
+#undef X
+  return 1;
+}
+
+// ================================================================ best poses
+
+__global__ void __launch_bounds__(64) best_kernel(BestArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int LPP = 64, APL = 2;
+  const int lig = blockIdx.x, r = threadIdx.x;
+  float* kE = reinterpret_cast<float*>(smem);
+  int* kI = reinterpret_cast<int*>(kE + a.t_pad);
+  float4* kept = reinterpret_cast<float4*>(smem + (size_t(a.t_pad) * 8 + 15) / 16 * 16);  // [top_n][kMaxAtoms]
+  const LigDev lg = a.L.ligs[lig];
+  PocketDev none;
+  none.preset = DOCK_PRESET_TRIDS;
+  none.n_terms = 0;
+  LaneLig<APL> L;
+  load_lane_lig<LPP, APL>(L, lg, a.L.atoms, a.L.frags, a.L.tors, none, r);
+  const int T = a.n_traj;
+  for (int i = r; i < a.t_pad; i += 64) {
+    float e = i < T ? a.E_best[size_t(lig) * T + i] : INFINITY;
+    if (!(e < INFINITY)) e = INFINITY;  // NaN and +inf rank last
+    kE[i] = e;
+    kI[i] = i < T ? i : 0x7fffffff;
+  }
+  wave_sync();
+  for (int k = 2; k <= a.t_pad; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = r; i < a.t_pad; i += 64) {
+        const int l = i ^ j;
+        if (l > i) {
+          const float ei = kE[i], el = kE[l];
+          const int ii = kI[i], il = kI[l];
+          const bool gt = ei > el || (ei == el && ii > il);
+          const bool up = (i & k) == 0;
+          if (gt == up) {
+            kE[i] = el; kE[l] = ei;
+            kI[i] = il; kI[l] = ii;
+          }
+        }
+      }
+      wave_sync();
+    }
+  }
+  int n_kept = 0;
+  const float inv_n = 1.0f / float(lg.n_atoms);
+  for (int c = 0; c < T && n_kept < a.top_n; ++c) {
+    const float E = kE[c];
+    if (!(E < INFINITY)) break;
+    const int t = kI[c];
+    const float q = r < lg.n_dof ? a.q_best[(size_t(lig) * T + t) * a.q_stride + r] : 0.f;
+    float x[APL][3];
+    fk_place<LPP, APL>(L, q, r, x);
+    bool dup = false;
+    for (int k = 0; k < n_kept && !dup; ++k) {
+      float acc = 0.f;
+#pragma unroll
+      for (int s = 0; s < APL; ++s) {
+        const int atom = APL * r + s;
+        if (atom < lg.n_atoms) {
+          const float4 y = kept[k * kMaxAtoms + atom];
+          const float dx = x[s][0] - y.x, dy = x[s][1] - y.y, dz = x[s][2] - y.z;
+          acc += dx * dx + dy * dy + dz * dz;
+        }
+      }
+      dup = sqrtf(group_sum<64>(acc) * inv_n) < a.rmsd_cut;
+    }
+    if (!dup) {
+      const size_t o = size_t(lig) * a.top_n + n_kept;
+#pragma unroll
+      for (int s = 0; s < APL; ++s) {
+        const int atom = APL * r + s;
+        if (atom < lg.n_atoms) {
+          kept[n_kept * kMaxAtoms + atom] = make_float4(x[s][0], x[s][1], x[s][2], 0.f);
+          if (a.xyz_out) {
+            float* dst = a.xyz_out + o * a.xyz_stride + 3 * L.aorig[s];
+            dst[0] = x[s][0];
+            dst[1] = x[s][1];
+            dst[2] = x[s][2];
+          }
+        }
+      }
+      if (r == 0) {
+        if (a.E_out) a.E_out[o] = E;
+        if (a.E_screen) a.E_screen[o] = E / (1.0f + a.w_tor * float(lg.n_tors));
+        if (a.idx_out) a.idx_out[o] = t;
+      }
+      if (a.q_out && r < a.q_stride) a.q_out[o * a.q_stride + r] = r < lg.n_dof ? q : 0.f;
+      ++n_kept;
+    }
+    wave_sync();
+  }
+  for (int k = n_kept; k < a.top_n; ++k) {
+    const size_t o = size_t(lig) * a.top_n + k;
+    if (r == 0) {
+      if (a.E_out) a.E_out[o] = INFINITY;
+      if (a.E_screen) a.E_screen[o] = INFINITY;
+      if (a.idx_out) a.idx_out[o] = -1;
+    }
+    if (a.q_out && r < a.q_stride) a.q_out[o * a.q_stride + r] = 0.f;
+  }
+  if (r == 0 && a.n_out) a.n_out[lig] = n_kept;
+}
+
+hipError_t launch_best(const BestArgs& a, hipStream_t s) {
+  const size_t lds = (size_t(a.t_pad) * 8 + 15) / 16 * 16 + size_t(a.top_n) * kMaxAtoms * 16;
+  if (a.n_ligands <= 0) return hipSuccess;
+  hipLaunchKernelGGL(best_kernel, dim3(a.n_ligands), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+// ================================================================ Philox dump
+
+__global__ void philox_kernel(const uint4* ctr, uint32_t k0, uint32_t k1, long long n, uint4* out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = philox4x32_10(ctr[i], k0, k1);
+}
+
+hipError_t launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, long long n, uint32_t* out,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(philox_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const uint4*>(ctr), k0, k1, n, reinterpret_cast<uint4*>(out));
+  return hipGetLastError();
+}
+
+// ================================================================ small helpers
+
+__global__ void fill_int_kernel(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void add_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p += v;
+}
+
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_add_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(add_int_kernel, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+}  // namespace dock

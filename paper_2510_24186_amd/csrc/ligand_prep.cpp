@@ -1,0 +1,284 @@
+// Host-side ligand preparation: atom typing, rigid fragments, torsion tree,
+// intra-ligand pair list and the depth-first packing used by the kernels.
+//
+// The DOFs are translation, rotation and one torsion per rotatable bond
+// (Methods, "Conformation sampling"; N_tor in E_screen).  The tree rules
+// (root of smallest height, breadth-first torsion order, >= 4-bond pairs in
+// different fragments) are stated in include/dock.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <set>
+
+#include "dock_internal.h"
+
+namespace dock {
+
+namespace {
+
+// Type radii (Angstrom) and flags; order C_H C_P N_P N_D N_A O_A O_DA Cl_H.
+const double kRadius[kTypes] = {1.9, 1.9, 1.8, 1.8, 1.8, 1.7, 1.7, 1.8};
+const bool kHydrophobic[kTypes] = {true, false, false, false, false, false, false, true};
+const bool kDonor[kTypes] = {false, false, false, true, false, false, true, false};
+const bool kAcceptor[kTypes] = {false, false, false, false, true, true, true, false};
+
+enum { T_C_H, T_C_P, T_N_P, T_N_D, T_N_A, T_O_A, T_O_DA, T_CL_H };
+
+std::vector<int> bfs_levels(const std::vector<std::vector<int>>& adj, int src) {
+  std::vector<int> d(adj.size(), -1);
+  std::deque<int> q{src};
+  d[src] = 0;
+  while (!q.empty()) {
+    int u = q.front();
+    q.pop_front();
+    for (int v : adj[u])
+      if (d[v] < 0) {
+        d[v] = d[u] + 1;
+        q.push_back(v);
+      }
+  }
+  return d;
+}
+
+}  // namespace
+
+void type_pair_table(int preset, TypePair table[kTypes * kTypes]) {
+  for (int a = 0; a < kTypes; ++a)
+    for (int b = 0; b < kTypes; ++b) {
+      TypePair& tp = table[a * kTypes + b];
+      bool hb = (kDonor[a] && kAcceptor[b]) || (kAcceptor[a] && kDonor[b]);
+      bool hyd = kHydrophobic[a] && kHydrophobic[b];
+      tp.rsum64 = kRadius[a] + kRadius[b];
+      tp.dclash64 = (preset == DOCK_PRESET_TRIDS && hb) ? 2.6 : tp.rsum64;
+      tp.rsum = float(tp.rsum64);
+      tp.dclash = float(tp.dclash64);
+      tp.dclash2 = tp.dclash * tp.dclash;
+      tp.flags = (hb ? 1u : 0u) | (hyd ? 2u : 0u);
+    }
+}
+
+void preset_weights(int preset, float* w, int* K) {
+  if (preset == DOCK_PRESET_TRIDS) {
+    const float v[3] = {0.2f, 10.0f, 0.6f};
+    std::memcpy(w, v, sizeof v);
+    *K = 3;
+  } else {
+    const float v[5] = {-0.0356f, -0.00516f, 0.840f, -0.0351f, -0.587f};
+    std::memcpy(w, v, sizeof v);
+    *K = 5;
+  }
+}
+
+int prepare_ligand(int n, const uint8_t* element, const uint8_t* n_h, const float* xyz,
+                   int n_bonds, const int32_t* bonds, const uint8_t* rotatable,
+                   const float* box_min, const float* box_max, LigandHost& L, std::string& err) {
+  if (n < 1) {
+    err = "ligand has no atoms";
+    return DOCK_E_TOPOLOGY;
+  }
+  if (n > kMaxAtoms) {
+    err = "ligand has " + std::to_string(n) + " atoms > " + std::to_string(kMaxAtoms);
+    return DOCK_E_LIMIT;
+  }
+  for (int i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(xyz[i])) {
+      err = "non-finite ligand coordinate";
+      return DOCK_E_TOPOLOGY;
+    }
+  for (int i = 0; i < n; ++i)
+    if (element[i] > 3) {
+      err = "unknown element code " + std::to_string(element[i]);
+      return DOCK_E_ARG;
+    }
+  std::vector<std::vector<int>> adj(n), rigid(n);
+  std::set<std::pair<int, int>> seen;
+  int n_rot = 0;
+  for (int b = 0; b < n_bonds; ++b) {
+    int i = bonds[2 * b], j = bonds[2 * b + 1];
+    if (i < 0 || j < 0 || i >= n || j >= n || i == j) {
+      err = "bad bond (" + std::to_string(i) + ", " + std::to_string(j) + ")";
+      return DOCK_E_TOPOLOGY;
+    }
+    auto key = std::make_pair(std::min(i, j), std::max(i, j));
+    if (!seen.insert(key).second) {
+      err = "duplicate bond";
+      return DOCK_E_TOPOLOGY;
+    }
+    adj[i].push_back(j);
+    adj[j].push_back(i);
+    if (rotatable[b]) {
+      ++n_rot;
+    } else {
+      rigid[i].push_back(j);
+      rigid[j].push_back(i);
+    }
+  }
+  {
+    auto d = bfs_levels(adj, 0);
+    for (int v : d)
+      if (v < 0) {
+        err = "disconnected ligand";
+        return DOCK_E_TOPOLOGY;
+      }
+  }
+  if (n_rot > kMaxTors) {
+    err = "too many rotatable bonds (" + std::to_string(n_rot) + ")";
+    return DOCK_E_LIMIT;
+  }
+  L = LigandHost();
+  L.n_atoms = n;
+  L.x0.assign(xyz, xyz + 3 * n);
+
+  // typing
+  L.type.resize(n);
+  for (int a = 0; a < n; ++a) {
+    int e = element[a];
+    int t;
+    if (e == 0) {
+      bool polar = false;
+      for (int b : adj[a]) polar |= (element[b] == 1 || element[b] == 2);
+      t = polar ? T_C_P : T_C_H;
+    } else if (e == 1) {
+      t = n_h[a] >= 1 ? T_N_D : (adj[a].size() <= 2 ? T_N_A : T_N_P);
+    } else if (e == 2) {
+      t = n_h[a] >= 1 ? T_O_DA : T_O_A;
+    } else {
+      t = T_CL_H;
+    }
+    L.type[a] = uint8_t(t);
+  }
+
+  // rigid fragments, ids in order of their lowest atom
+  L.atom_frag.assign(n, -1);
+  int F = 0;
+  for (int a = 0; a < n; ++a) {
+    if (L.atom_frag[a] >= 0) continue;
+    auto d = bfs_levels(rigid, a);
+    for (int b = 0; b < n; ++b)
+      if (d[b] >= 0) L.atom_frag[b] = F;
+    ++F;
+  }
+  L.n_frags = F;
+  // fragment tree
+  std::vector<std::vector<int>> fadj(F);
+  std::set<std::pair<int, int>> fseen;
+  std::vector<std::vector<std::pair<int, int>>> fbond(F);  // (neighbour frag, atom in this frag)
+  for (int b = 0; b < n_bonds; ++b) {
+    if (!rotatable[b]) continue;
+    int i = bonds[2 * b], j = bonds[2 * b + 1];
+    int fi = L.atom_frag[i], fj = L.atom_frag[j];
+    auto key = std::make_pair(std::min(fi, fj), std::max(fi, fj));
+    if (fi == fj || !fseen.insert(key).second) {
+      err = "rotatable bond inside a ring";
+      return DOCK_E_TOPOLOGY;
+    }
+    fadj[fi].push_back(fj);
+    fadj[fj].push_back(fi);
+    fbond[fi].push_back({fj, i});
+    fbond[fj].push_back({fi, j});
+  }
+  if (int(fseen.size()) != F - 1) {
+    err = "fragment graph is not a tree";
+    return DOCK_E_TOPOLOGY;
+  }
+  for (auto& v : fadj) std::sort(v.begin(), v.end());
+  int best = 1 << 30, root = 0;
+  for (int f = 0; f < F; ++f) {
+    auto d = bfs_levels(fadj, f);
+    int h = *std::max_element(d.begin(), d.end());
+    if (h < best) {
+      best = h;
+      root = f;
+    }
+  }
+  L.root = root;
+  L.height = best;
+  // breadth-first order from the root, children by id
+  L.frag_parent.assign(F, -1);
+  std::vector<char> vis(F, 0);
+  std::deque<int> q{root};
+  vis[root] = 1;
+  L.bfs.push_back(root);
+  while (!q.empty()) {
+    int u = q.front();
+    q.pop_front();
+    for (int v : fadj[u])
+      if (!vis[v]) {
+        vis[v] = 1;
+        L.frag_parent[v] = u;
+        L.bfs.push_back(v);
+        q.push_back(v);
+      }
+  }
+  auto atom_toward = [&](int f, int other) {
+    for (auto& pr : fbond[f])
+      if (pr.first == other) return pr.second;
+    return -1;
+  };
+  for (size_t k = 1; k < L.bfs.size(); ++k) {
+    int f = L.bfs[k], p = L.frag_parent[f];
+    L.tors_frag.push_back(f);
+    L.tors_a.push_back(atom_toward(p, f));
+    L.tors_b.push_back(atom_toward(f, p));
+  }
+  L.n_tors = int(L.tors_frag.size());
+
+  // intra-ligand pairs
+  for (int i = 0; i < n; ++i) {
+    auto d = bfs_levels(adj, i);
+    for (int j = i + 1; j < n; ++j)
+      if (L.atom_frag[i] != L.atom_frag[j] && d[j] >= 4) {
+        L.pair_i.push_back(i);
+        L.pair_j.push_back(j);
+      }
+  }
+
+  // centroid of the root fragment (FP64) and the translation box
+  int cnt = 0;
+  for (int a = 0; a < n; ++a)
+    if (L.atom_frag[a] == root) {
+      for (int c = 0; c < 3; ++c) L.c0[c] += double(xyz[3 * a + c]);
+      ++cnt;
+    }
+  for (int c = 0; c < 3; ++c) L.c0[c] /= cnt;
+  for (int c = 0; c < 3; ++c) {
+    float lo = xyz[c], hi = xyz[c];
+    for (int a = 1; a < n; ++a) {
+      lo = std::min(lo, xyz[3 * a + c]);
+      hi = std::max(hi, xyz[3 * a + c]);
+    }
+    L.box_min[c] = box_min ? box_min[c] : lo;
+    L.box_max[c] = box_max ? box_max[c] : hi;
+    if (!(L.box_min[c] <= L.box_max[c]) || !std::isfinite(L.box_min[c]) ||
+        !std::isfinite(L.box_max[c])) {
+      err = "invalid translation box";
+      return DOCK_E_ARG;
+    }
+  }
+
+  // depth-first pre-order of fragments (children by id) -> atom packing
+  std::vector<std::vector<int>> kids(F);
+  for (int f : L.bfs)
+    if (L.frag_parent[f] >= 0) kids[L.frag_parent[f]].push_back(f);
+  for (auto& v : kids) std::sort(v.begin(), v.end());
+  std::vector<int> stack{root};
+  while (!stack.empty()) {
+    int f = stack.back();
+    stack.pop_back();
+    L.dfs_frag.push_back(f);
+    for (auto it = kids[f].rbegin(); it != kids[f].rend(); ++it) stack.push_back(*it);
+  }
+  L.frag_new.assign(F, -1);
+  for (int i = 0; i < F; ++i) L.frag_new[L.dfs_frag[i]] = i;
+  L.atom_new.assign(n, -1);
+  for (int f : L.dfs_frag)
+    for (int a = 0; a < n; ++a)
+      if (L.atom_frag[a] == f) {
+        L.atom_new[a] = int(L.dfs_atom.size());
+        L.dfs_atom.push_back(a);
+      }
+  return DOCK_OK;
+}
+
+}  // namespace dock

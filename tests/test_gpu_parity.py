@@ -1,0 +1,212 @@
+"""GPU parity tests: the HIP library (through the C ABI) against the FP64
+oracle, on seeded synthetic inputs.  Run on an MI355X.
+
+* Philox blocks bit-exact;
+* grid maps against brute-force node sums (full tiny grid, sampled nodes of
+  the 600- and 2,000-atom pockets, both presets);
+* score + gradient per evaluation on seeded poses: tiny, 24-atom, ragged
+  mixes over every lane configuration, and all 256 ligands of the screening
+  workload at full size;
+* sampler: initial poses from the Philox stream, pure Metropolis (L = 0)
+  trajectories coupled step by step with the oracle's.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import topology, maps as MAPS, score as SC, sampler as SM, params as P, philox as PX
+from tests import _gpu as G
+from tests._tiny import tiny_pocket, tiny_ligand
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return G.lib()
+
+
+def test_philox_blocks_bit_exact(D):
+    G.say("philox: 4096 counters")
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64)
+    ctr[:4] = [[0, 0, 0, 0], [1, 0, 0, 0], [2 ** 32 - 1] * 4, [7, 200, 1, 0]]
+    k0, k1 = 0x12345678, 0x9ABCDEF0
+    out = D.dock_philox(torch.tensor(ctr.astype(np.uint32).view(np.int32), device="cuda"), k0, k1)
+    got = out.cpu().numpy().view(np.uint32)
+    ref = np.stack(PX.philox4x32_10([ctr[:, i] for i in range(4)], [k0, k1]), 1)
+    assert np.array_equal(got, ref)
+
+
+def _map_check(gpu, ref_G, w, tag):
+    """gpu: [8, n] combined values; ref_G: [8, K, n] oracle per-term sums."""
+    M_ref = np.einsum("k,tkn->tn", np.asarray(w, np.float64), ref_G)
+    S_abs = np.einsum("k,tkn->tn", np.abs(np.asarray(w, np.float64)), np.abs(ref_G))
+    err = np.abs(gpu - M_ref)
+    # FP64 terms and sums rounded once to FP32: within one FP32 ulp of the
+    # oracle's FP64 value (plus FP64 summation-order noise)
+    ulp = np.spacing(np.abs(M_ref).astype(np.float32)).astype(np.float64)
+    tol = ulp + 1e-12 * np.maximum(S_abs, 1.0)
+    bad = err > tol
+    G.say(tag, "max err", err.max(), "max err/tol", (err / tol).max())
+    assert not bad.any(), (tag, np.argwhere(bad)[:5], gpu[bad][:5], M_ref[bad][:5])
+
+
+@pytest.mark.parametrize("preset", [P.PRESET_TRIDS, P.PRESET_VINA])
+def test_maps_full_tiny_grid(D, preset):
+    G.say("maps tiny grid preset", preset)
+    pk = tiny_pocket(n=40, radius=7.0, grid=24)
+    w = G.weights32(preset)
+    p = G.load_pocket(pk, preset, w, keep=True)
+    M = D.dock_pocket_maps(p).cpu().numpy().reshape(8, -1)
+    Gt = D.dock_pocket_maps(p, per_term=True).cpu().numpy().reshape(8, P.n_terms(preset), -1)
+    ref = MAPS.build_maps(pk, preset).reshape(8, P.n_terms(preset), -1)
+    _map_check(M, ref, w, "tiny")
+    # per-term maps: FP64 sums rounded once
+    ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(Gt - ref) <= ulp + 1e-12)
+
+
+@pytest.mark.parametrize("name,preset", [("C1", P.PRESET_TRIDS), ("C2", P.PRESET_TRIDS),
+                                         ("C2", P.PRESET_VINA)])
+def test_maps_sampled_nodes(D, name, preset):
+    pk = synth.workload(name, n_lig=1)[0][0]
+    G.say("maps sampled nodes", name, preset, pk.dims)
+    w = G.weights32(preset)
+    p = G.load_pocket(pk, preset, w)
+    M = D.dock_pocket_maps(p).cpu().numpy().reshape(8, -1)
+    rng = np.random.default_rng(1)
+    nodes = rng.choice(M.shape[1], 3000, replace=False)
+    ref = MAPS.build_maps(pk, preset, nodes=nodes)
+    _map_check(M[:, nodes], ref, w, name)
+
+
+def _score_case(D, pk, L, preset, n_per, kinds, rng, tag, lazy=False):
+    w = G.weights32(preset)
+    p = G.load_pocket(pk, preset, w)
+    H = G.load_ligands(L)
+    sc = (SC.LazyScorer if lazy else SC.Scorer)(pk, preset, weights=w.astype(np.float64))
+    topos = [topology.from_ligands(L, i) for i in range(L.n_ligands)]
+    qs = H.q_stride
+    rows, lig = [], []
+    for i, t in enumerate(topos):
+        for kind in kinds:
+            q = G.poses_for(t, n_per, rng, kind)
+            qq = np.zeros((n_per, qs), np.float32)
+            qq[:, :t.n_dof] = q
+            rows.append(qq)
+            lig += [i] * n_per
+    Q = np.concatenate(rows)
+    G.say(tag, "poses", len(Q), "ligands", L.n_ligands)
+    E, g, xyz = D.dock_score_grad(p, H, torch.tensor(np.array(lig, np.int32), device="cuda"),
+                                  torch.tensor(Q, device="cuda"), want_xyz=True)
+    torch.cuda.synchronize()
+    E, g, xyz = E.cpu().numpy(), g.cpu().numpy(), xyz.cpu().numpy()
+    lig = np.array(lig)
+    checked = skipped = 0
+    worst = [0.0, 0.0]
+    worst_x = 0.0
+    for i, t in enumerate(topos):
+        sel = lig == i
+        ref = sc.score(t, Q[sel][:, :t.n_dof].astype(np.float64))
+        c, s, we, wg = G.compare_eval(E[sel], g[sel], ref, t.n_dof, "%s lig %d" % (tag, i))
+        checked += c
+        skipped += s
+        worst = [max(worst[0], we), max(worst[1], wg)]
+        # coordinates in the caller's atom order
+        dx = np.abs(xyz[sel][:, :t.n_atoms] - ref["x"]).max(initial=0)
+        worst_x = max(worst_x, dx)
+        assert dx <= 2e-5, (tag, i, dx)
+        # DOF slots past n_dof are left untouched (zero)
+        assert np.all(g[sel][:, t.n_dof:] == 0)
+    G.say(tag, "checked", checked, "gradient margin-skipped", skipped,
+          "worst E/tol %.3g g/tol %.3g" % tuple(worst), "max |dx| %.3g A" % worst_x)
+    assert skipped <= max(2, 0.03 * (checked + skipped))
+
+
+def test_score_grad_tiny(D):
+    pk = tiny_pocket(n=20, radius=6.0, grid=28)
+    L = synth.pack_ligands([synth.make_ligand(n, t, np.random.default_rng(n)) for n, t in
+                            ((1, 0), (2, 0), (6, 2), (9, 3))])
+    L.pocket_index = np.zeros(L.n_ligands, np.int32)
+    _score_case(D, pk, L, P.PRESET_TRIDS, 16, ("uniform", "near", "outside"),
+                np.random.default_rng(2), "tiny")
+
+
+@pytest.mark.parametrize("preset", [P.PRESET_TRIDS, P.PRESET_VINA])
+def test_score_grad_c1(D, preset):
+    pk, L, _ = synth.workload("C1")
+    _score_case(D, pk[0], L, preset, 64, ("uniform", "near", "outside"), np.random.default_rng(3),
+                "C1/%d" % preset)
+
+
+def test_score_grad_ragged_all_lane_configs(D):
+    # sizes that select 16-, 32- and 64-lane groups and two atoms per lane
+    spec = [(10, 0), (14, 9), (16, 10), (17, 2), (30, 12), (33, 3), (45, 15), (64, 20), (65, 4),
+            (90, 12), (128, 31)]
+    parts = [synth.make_ligand(n, t, np.random.default_rng(40 + n)) for n, t in spec]
+    L = synth.pack_ligands(parts)
+    L.pocket_index = np.zeros(L.n_ligands, np.int32)
+    pk = synth.make_pocket(800, grid=48, seed=9)
+    _score_case(D, pk, L, P.PRESET_TRIDS, 12, ("uniform", "near"), np.random.default_rng(4),
+                "ragged", lazy=True)
+
+
+def test_score_grad_screening_workload_full(D):
+    # all 256 ligands of the 2,000-atom screening workload, one near-input and
+    # one uniform pose each, oracle maps computed at the nodes the poses touch
+    pk, L, _ = synth.workload("C2")
+    _score_case(D, pk[0], L, P.PRESET_TRIDS, 1, ("uniform", "near"), np.random.default_rng(5),
+                "C2-full", lazy=True)
+
+
+def test_sampler_initial_poses_and_scores(D):
+    pk, L, _ = synth.workload("C1")
+    G.say("sampler init C1: 64 trajectories")
+    w = G.weights32(P.PRESET_TRIDS)
+    p = G.load_pocket(pk[0], P.PRESET_TRIDS, w)
+    H = G.load_ligands(L)
+    run = D.dock_sample(p, H, n_traj=64, n_steps=0, seed=11)
+    st = D.dock_run_state(run)
+    topo = topology.from_ligands(L, 0)
+    q0 = SM.initial_q(topo, 0, 11, np.arange(64))
+    qg = st["q_cur"].cpu().numpy()[0, :, :topo.n_dof]
+    np.testing.assert_allclose(qg, q0, rtol=0, atol=4e-6 * np.maximum(1, np.abs(q0)).max())
+    sc = SC.Scorer(pk[0], weights=w.astype(np.float64))
+    ref = sc.score(topo, q0)
+    Eg = st["E_cur"].cpu().numpy()[0]
+    G.compare_eval(Eg, np.zeros((64, topo.n_dof)) + ref["dEdq"], ref, topo.n_dof, "init")
+    assert np.all(st["n_evals"].cpu().numpy() == 1)
+
+
+def test_sampler_pure_metropolis_coupled(D):
+    """L = 0: every step resamples one DOF from the shared Philox stream and
+    accepts on the Metropolis test; GPU and oracle trajectories agree unless a
+    decision margin is below FP32 resolution."""
+    pk = tiny_pocket(n=20, radius=6.0, grid=28)
+    L = tiny_ligand(9, 3, seed=6)
+    L.pocket_index = np.zeros(1, np.int32)
+    w = G.weights32(P.PRESET_TRIDS)
+    p = G.load_pocket(pk, P.PRESET_TRIDS, w)
+    H = G.load_ligands(L)
+    T, S = 48, 30
+    G.say("pure MC coupled: T", T, "S", S)
+    run = D.dock_sample(p, H, n_traj=T, n_steps=S, n_local=0, seed=3)
+    st = D.dock_run_state(run)
+    topo = topology.from_ligands(L, 0)
+    sc = SC.Scorer(pk, weights=w.astype(np.float64))
+    prm = SM.SamplerParams(n_traj=T, n_steps=S, n_local=0, seed=3)
+    trace = []
+    ost = SM.sample(sc, topo, 0, prm, trace=trace)
+    margin = np.min(np.stack([t["margin"] for t in trace]), axis=0)
+    Eb = st["E_best"].cpu().numpy()[0]
+    qb = st["q_best"].cpu().numpy()[0, :, :topo.n_dof]
+    agree = np.abs(Eb - ost.E_best) <= 1e-4 * np.maximum(1.0, np.abs(ost.E_best))
+    agree &= np.all(np.abs(qb - ost.q_best) <= 1e-4 * np.maximum(1.0, np.abs(ost.q_best)), axis=1)
+    G.say("agree", agree.sum(), "/", T, "min margin of disagreeing", margin[~agree] if (~agree).any() else "-")
+    assert np.all(agree | (margin < 1e-3))
+    assert agree.sum() >= T - 2
+    assert np.all(st["n_evals"].cpu().numpy() == 1 + S)

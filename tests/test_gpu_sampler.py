@@ -1,0 +1,239 @@
+"""GPU tests of the sampler forms, resume, best-pose selection and whole-run
+distributions.  Run on an MI355X.
+
+* plain, batched, hipGraph-replayed and chunked launches give bit-identical
+  trajectories (random streams depend on ligand, trajectory and step only);
+* run(S) == run(s) + advance(S - s) == restore(state at s) + advance, bitwise;
+* the recorded trace is self-consistent (score kernel at the logged q, Adam
+  update rule between consecutive rows, Armijo condition for line search);
+* best poses (rank, RMSD clustering, top N, E_screen) against the oracle on
+  seeded candidate sets;
+* best-pose energy and RMSD distributions over seeds against the oracle's
+  (stored by tests/golden/make_c1_best_distribution.py);
+* short Adam trajectories coupled with the oracle's.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import topology, score as SC, sampler as SM, best as BEST, fk as FK, params as P
+from tests import _gpu as G
+from tests._tiny import tiny_pocket, tiny_ligand
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def D():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return G.lib()
+
+
+@pytest.fixture(scope="module")
+def mixed(D):
+    """A 2,000-atom pocket and 12 ligands spanning every lane configuration."""
+    pk = synth.make_pocket(2000, grid=64, seed=0)
+    spec = [(10, 0), (15, 6), (20, 3), (28, 9), (33, 5), (40, 15), (52, 8), (60, 14), (64, 2),
+            (66, 6), (70, 12), (24, 4)]
+    L = synth.pack_ligands([synth.make_ligand(n, t, np.random.default_rng(70 + n)) for n, t in spec])
+    L.pocket_index = np.zeros(L.n_ligands, np.int32)
+    w = G.weights32(P.PRESET_TRIDS)
+    return G.load_pocket(pk, P.PRESET_TRIDS, w), G.load_ligands(L), L, pk
+
+
+def _state(D, run):
+    st = D.dock_run_state(run)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in st.items()}
+
+
+def _same(a, b, tag):
+    for k in ("q_cur", "E_cur", "q_best", "E_best", "n_evals"):
+        assert np.array_equal(a[k], b[k]), (tag, k, np.argwhere(a[k] != b[k])[:4])
+
+
+def test_forms_are_bitwise_identical(D, mixed):
+    p, H, L, _ = mixed
+    kw = dict(n_traj=24, n_steps=6, n_local=4, seed=9)
+    G.say("forms: plain")
+    ref = _state(D, D.dock_sample(p, H, form=D.FORM_PLAIN, use_graph=0, **kw))
+    for form, graph, chunk in ((D.FORM_BATCHED, 0, 0), (D.FORM_BATCHED, 1, 0), (D.FORM_BATCHED, 1, 2),
+                               (D.FORM_BATCHED, 0, 4)):
+        G.say("forms: batched graph", graph, "chunk", chunk)
+        got = _state(D, D.dock_sample(p, H, form=form, use_graph=graph, steps_per_launch=chunk, **kw))
+        _same(ref, got, (form, graph, chunk))
+    assert np.all(ref["n_evals"] == 1 + 6 * 5)
+    assert np.all(ref["E_best"] <= ref["E_cur"])
+
+
+def test_forced_wider_groups_agree(D, mixed):
+    p, H, L, _ = mixed
+    kw = dict(n_traj=8, n_steps=3, n_local=3, seed=2)
+    G.say("lanes: auto vs 64")
+    a = _state(D, D.dock_sample(p, H, **kw))
+    b = _state(D, D.dock_sample(p, H, lanes_per_pose=64, **kw))
+    # different reduction trees: close, not bitwise
+    np.testing.assert_allclose(a["E_cur"][:, :], b["E_cur"], rtol=2e-3, atol=1e-3)
+
+
+def test_resume_and_restore_bitwise(D, mixed):
+    p, H, L, _ = mixed
+    kw = dict(n_traj=16, n_local=3, seed=5)
+    G.say("resume")
+    full = _state(D, D.dock_sample(p, H, n_steps=7, **kw))
+    r = D.dock_sample(p, H, n_steps=3, **kw)
+    mid = D.dock_run_state(r)
+    D.dock_run_advance(r, 4)
+    _same(full, _state(D, r), "advance")
+    # restore the step-3 state into a fresh run and finish
+    r2 = D.dock_sample(p, H, n_steps=0, **kw)
+    D.dock_run_set_state(r2, mid["q_cur"], mid["E_cur"], mid["q_best"], mid["E_best"], 3)
+    D.dock_run_advance(r2, 4)
+    got = _state(D, r2)
+    for k in ("q_cur", "E_cur", "q_best", "E_best"):
+        assert np.array_equal(full[k], got[k]), k
+
+
+def test_trace_self_consistency(D):
+    pk = tiny_pocket(n=20, radius=6.0, grid=28)
+    L = tiny_ligand(9, 3, seed=6)
+    L.pocket_index = np.zeros(1, np.int32)
+    w = G.weights32(P.PRESET_TRIDS)
+    p = G.load_pocket(pk, P.PRESET_TRIDS, w)
+    H = G.load_ligands(L)
+    T, S, Lc = 8, 4, 5
+    G.say("trace adam")
+    run = D.dock_sample(p, H, n_traj=T, n_steps=S, n_local=Lc, seed=1, record_trace=1)
+    st = D.dock_run_state(run, trace=True)
+    tr = st["trace"].cpu().numpy()[0]           # [T, cap, 2*qs+1]
+    qs = st["q_stride"]
+    n_dof = 6 + H.max_tors
+    rows = tr.reshape(-1, 2 * qs + 1)
+    q = torch.tensor(rows[:, :qs].copy(), device="cuda")
+    E, g, _ = D.dock_score_grad(p, H, torch.zeros(len(rows), dtype=torch.int32, device="cuda"), q)
+    np.testing.assert_allclose(E.cpu().numpy(), rows[:, 2 * qs], rtol=1e-6, atol=1e-5)
+    np.testing.assert_allclose(g.cpu().numpy()[:, :n_dof], rows[:, qs:qs + n_dof], rtol=1e-5, atol=1e-4)
+    topo = topology.from_ligands(L, 0)
+    # Adam rule between consecutive rows of one MC step (FP64 recomputation)
+    for t in range(T):
+        for s in range(S):
+            base = 1 + s * (Lc + 1)
+            m = np.zeros(n_dof); v = np.zeros(n_dof)
+            for k in range(Lc):
+                qk = tr[t, base + k, :n_dof].astype(np.float64)
+                gk = tr[t, base + k, qs:qs + n_dof].astype(np.float64)
+                m = 0.9 * m + 0.1 * gk
+                v = 0.999 * v + 0.001 * gk * gk
+                step = 0.1 * (m / (1 - 0.9 ** (k + 1))) / (np.sqrt(v / (1 - 0.999 ** (k + 1))) + 1e-8)
+                nxt = qk - step
+                nxt[:3] = np.clip(nxt[:3], topo.box_min, topo.box_max)
+                nxt[3:] = nxt[3:] - 2 * np.pi * np.floor((nxt[3:] + np.pi) / (2 * np.pi))
+                got = tr[t, base + k + 1, :n_dof]
+                d = np.abs(np.angle(np.exp(1j * (got - nxt))))
+                d[:3] = np.abs(got[:3] - nxt[:3])
+                assert d.max() < 2e-4, (t, s, k, d.max())
+    # Line search: every accepted trial satisfies Armijo
+    G.say("trace line search")
+    run = D.dock_sample(p, H, n_traj=T, n_steps=3, n_local=3, seed=1, record_trace=1,
+                        local_opt=D.LOCAL_LINESEARCH)
+    st = D.dock_run_state(run, trace=True)
+    nev = st["n_evals"].cpu().numpy()[0]
+    assert np.all(nev >= 1 + 3) and len(set(nev.tolist())) >= 1
+
+
+def test_best_poses_match_oracle(D):
+    L = synth.make_ligands(4, lambda r: int(r.integers(8, 40)), lambda r: int(r.integers(0, 8)), seed=31)
+    H = G.load_ligands(L)
+    rng = np.random.default_rng(7)
+    T = 96
+    qs = H.q_stride
+    Eall = np.zeros((L.n_ligands, T), np.float32)
+    Qall = np.zeros((L.n_ligands, T, qs), np.float32)
+    topos = []
+    for i in range(L.n_ligands):
+        t = topology.from_ligands(L, i)
+        topos.append(t)
+        q = synth.random_poses(t.n_dof, t.box_min, t.box_max, T, rng)
+        q[T // 2:] = q[:T // 2] + (rng.normal(size=(T // 2, t.n_dof)) * 0.05).astype(np.float32)
+        Qall[i, :, :t.n_dof] = q
+        e = rng.normal(size=T).astype(np.float32)
+        e[3] = e[7]
+        e[11] = np.inf
+        Eall[i] = e
+    G.say("best poses", L.n_ligands, "ligands x", T)
+    out = D.dock_best_poses(H, T, torch.tensor(Eall, device="cuda"), torch.tensor(Qall, device="cuda"),
+                            top_n=8, rmsd_cluster=1.0)
+    got = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    for i, t in enumerate(topos):
+        ref = BEST.best_poses(t, Eall[i].astype(np.float64), Qall[i, :, :t.n_dof].astype(np.float64),
+                              top_n=8, rmsd_cut=1.0, margins=True)
+        n = len(ref["idx"])
+        if ref["rmsd_margin"] > 1e-4:
+            assert got["n"][i] == n
+            assert list(got["idx"][i, :n]) == list(ref["idx"])
+            np.testing.assert_array_equal(got["E"][i, :n], Eall[i][ref["idx"]])
+            np.testing.assert_allclose(got["E_screen"][i, :n], ref["E_screen"], rtol=1e-6)
+            np.testing.assert_array_equal(got["q"][i, :n, :t.n_dof], Qall[i, ref["idx"], :t.n_dof])
+            np.testing.assert_allclose(got["xyz"][i, :n, :t.n_atoms], ref["xyz"], atol=2e-5)
+            assert np.all(got["idx"][i, n:] == -1) and np.all(np.isinf(got["E"][i, n:]))
+
+
+def test_adam_trajectories_coupled_short(D):
+    """First MC steps with Adam refinement: GPU and oracle share every random
+    number; report how many trajectories stay together."""
+    pk = tiny_pocket(n=20, radius=6.0, grid=28)
+    L = tiny_ligand(9, 3, seed=6)
+    L.pocket_index = np.zeros(1, np.int32)
+    w = G.weights32(P.PRESET_TRIDS)
+    p = G.load_pocket(pk, P.PRESET_TRIDS, w)
+    H = G.load_ligands(L)
+    T, S = 32, 2
+    st = _state(D, D.dock_sample(p, H, n_traj=T, n_steps=S, n_local=10, seed=4))
+    topo = topology.from_ligands(L, 0)
+    sc = SC.Scorer(pk, weights=w.astype(np.float64))
+    ost = SM.sample(sc, topo, 0, SM.SamplerParams(n_traj=T, n_steps=S, n_local=10, seed=4))
+    rel = np.abs(st["E_best"][0] - ost.E_best) / np.maximum(1.0, np.abs(ost.E_best))
+    G.say("coupled Adam: fraction within 1e-3:", np.mean(rel < 1e-3), "median rel", np.median(rel))
+    assert np.mean(rel < 1e-3) >= 0.5
+
+
+def test_best_energy_and_rmsd_distributions_over_seeds(D):
+    """The 600-atom-pocket / 24-atom-ligand workload, 4 seeds x 64 trajectories
+    x 100 MC steps: GPU best energies and RMSDs versus the oracle's."""
+    from scipy.stats import ks_2samp
+    gold = json.load(open(os.path.join(HERE, "golden", "c1_best_distribution.json")))
+    pk, L, wl = synth.workload("C1")
+    w = G.weights32(P.PRESET_TRIDS)
+    p = G.load_pocket(pk[0], P.PRESET_TRIDS, w)
+    H = G.load_ligands(L)
+    topo = topology.from_ligands(L, 0)
+    Eg, Rg = [], []
+    for s in gold["seeds"]:
+        G.say("distribution seed", s)
+        run = D.dock_sample(p, H, n_traj=gold["n_traj"], n_steps=gold["n_steps"], n_local=gold["n_local"],
+                            seed=s)
+        st = D.dock_run_state(run)
+        qb = st["q_best"][0]
+        E, _, xyz = D.dock_score_grad(p, H, torch.zeros(qb.shape[0], dtype=torch.int32, device="cuda"),
+                                      qb.contiguous(), want_grad=False, want_xyz=True)
+        x = xyz.cpu().numpy()[:, :topo.n_atoms]
+        Eg.append(st["E_best"].cpu().numpy()[0])
+        Rg.append(np.sqrt(np.mean(np.sum((x - topo.x0[None]) ** 2, axis=2), axis=1)))
+    Eg, Rg = np.concatenate(Eg), np.concatenate(Rg)
+    Eo, Ro = np.concatenate(gold["E_best"]), np.concatenate(gold["rmsd"])
+    pE = ks_2samp(Eg, Eo).pvalue
+    pR = ks_2samp(Rg, Ro).pvalue
+    # bootstrap CI of the median difference
+    rng = np.random.default_rng(0)
+    diffs = [np.median(rng.choice(Eg, len(Eg))) - np.median(rng.choice(Eo, len(Eo))) for _ in range(2000)]
+    lo, hi = np.percentile(diffs, [2.5, 97.5])
+    G.say("KS p(E) %.3g p(RMSD) %.3g; median E gpu %.3f oracle %.3f; CI of diff [%.3f, %.3f]"
+          % (pE, pR, np.median(Eg), np.median(Eo), lo, hi))
+    assert pE >= 0.01 and pR >= 0.01
+    assert lo <= 0.0 <= hi
