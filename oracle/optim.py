@@ -9,8 +9,9 @@ correction; L steps per MC step; moments restart at every MC step.
 LINESEARCH (the alternative local rule): steepest descent along the unit
 direction d = -g/|g|, alpha = 2^-j for j = 0..10, the first alpha with
   E(q + alpha d) <= E(q) + 1e-4 * alpha * (g . d)
-is taken, else the pose stays.  After every update the angles are wrapped
-to [-pi, pi) and the translation is clamped to the box.
+is taken; if none is, the pose stays and its refinement ends.  After every
+update the angles are wrapped to [-pi, pi) and the translation is clamped to
+the box.
 """
 import numpy as np
 
@@ -53,17 +54,21 @@ def adam_refine(score_fn, q, n_local, box_min, box_max, lr=P.ADAM_LR, b1=P.ADAM_
 
 
 def linesearch_refine(score_fn, q, n_local, box_min, box_max, n_evals=None):
-    """n_local Armijo steps; returns (q, E).  n_evals[p] counts evaluations."""
+    """n_local Armijo steps; returns (q, E).  n_evals[p] counts evaluations.
+
+    A search that finds no acceptable alpha ends the pose's refinement.
+    """
     q = np.array(q, np.float64, copy=True)
     E, g = score_fn(q)
     if n_evals is not None:
         n_evals += 1
+    stopped = np.zeros(len(q), bool)
     for _ in range(n_local):
         gn = np.linalg.norm(g, axis=1)
-        active = gn > 0
-        d = np.where(active[:, None], -g / np.where(active, gn, 1.0)[:, None], 0.0)
+        stopped |= ~(gn > 0)
+        d = np.where(stopped[:, None], 0.0, -g / np.where(stopped, 1.0, gn)[:, None])
         slope = np.einsum("pi,pi->p", g, d)
-        done = ~active
+        done = stopped.copy()
         newq, newE, newg = q.copy(), E.copy(), g.copy()
         alpha = 1.0
         for _j in range(LS_MAX_HALVINGS + 1):
@@ -77,5 +82,6 @@ def linesearch_refine(score_fn, q, n_local, box_min, box_max, n_evals=None):
             newq[ok], newE[ok], newg[ok] = cand[ok], Ec[ok], gc[ok]
             done |= ok
             alpha *= 0.5
+        stopped |= ~done
         q, E, g = newq, newE, newg
     return q, E
