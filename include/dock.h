@@ -158,6 +158,37 @@ int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligand
                     float* E, float* dEdq, float* xyz_out, int32_t xyz_stride, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Differentiable form.  The score is linear in the per-term maps and the
+ * weights (Methods, E_dock: a weighted sum of pairwise terms):
+ *   E = sum_k w_k (sum_i trilerp(G[t_i][k], x_i) + sum_pairs phi_k(r_ij)) + E_out
+ * dock_score_terms evaluates it with caller-supplied maps and weights;
+ * dock_score_adjoint ACCUMULATES (+=) the gradients of L = sum_p dLdE[p] E_p
+ *   dL/dG[t][k][node]  trilinear corner weights x w_k x dLdE (atomic scatter,
+ *                      summation order not deterministic),
+ *   dL/dw_k            dLdE x (per-term map sum + per-term pair sum),
+ *   dL/dx              dLdE x dE/dx (caller atom order), and
+ *   dL/dq              dLdE x dE/dq (DOF mode only),
+ * recomputing the forward kinematics from q instead of storing coordinates.
+ * Poses are given either as DOFs (q, q_stride; xyz = NULL) or as world
+ * coordinates (xyz, xyz_stride >= 3 * max atoms, caller atom order; q = NULL).
+ *   G      host array [n_pockets] of device pointers to [8][K][nz][ny][nx];
+ *          a NULL entry uses the pocket's kept per-term maps
+ *   w      device [n_pockets * K]
+ *   dLdG   host array [n_pockets] of device pointers (entries nullable) or NULL
+ *   dLdw   device [n_pockets * K] or NULL;  dLdq, dLdx device or NULL
+ * All pockets of a call share one preset; n_pockets <= 16.
+ * ---------------------------------------------------------------------- */
+int dock_score_terms(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
+                     int64_t n_poses, const int32_t* pose_lig, const float* q, int32_t q_stride,
+                     const float* xyz, int32_t xyz_stride, const float* const* G, const float* w,
+                     float* E, void* stream);
+int dock_score_adjoint(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
+                       int64_t n_poses, const int32_t* pose_lig, const float* q, int32_t q_stride,
+                       const float* xyz, int32_t xyz_stride, const float* const* G, const float* w,
+                       const float* dLdE, float* const* dLdG, float* dLdw, float* dLdq, float* dLdx,
+                       void* stream);
+
+/* ------------------------------------------------------------------------
  * Sampling (Methods, "Conformation sampling"; Fig. 2).  Each trajectory
  * starts from random DOFs, then each MC step resamples one scalar DOF
  * uniformly over its range, refines with n_local local steps (Adam, lr 0.1,
@@ -187,6 +218,22 @@ void dock_sample_params_default(dock_sample_params* p);
  * trajectory by p->n_steps MC steps.  The run owns its state buffers. */
 int dock_sample(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
                 const dock_sample_params* p, void* stream, dock_run_t* out);
+/* Autotuner.  For every lane configuration that L's ligands fall into
+ * (group width 16/32/64 lanes, 1-2 atoms per lane), times `trial_steps` MC
+ * steps of the batched sampler with p's settings for each candidate: blocks
+ * of 64, 128 or 256 threads (trajectories per workgroup = block / width) and
+ * the natural or the next wider group width.  The fastest is kept in a
+ * process-wide cache keyed by (GPU architecture, configuration) that
+ * dock_sample consults when lanes_per_pose == 0.  Random streams depend on
+ * (ligand, trajectory, step) only, so tuning never changes which numbers a
+ * trajectory draws.  Synchronizes `stream`. */
+int dock_autotune(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
+                  const dock_sample_params* p, int32_t trial_steps, void* stream);
+/* The cache as JSON text into buf (host, cap bytes, NUL-terminated);
+ * *needed (nullable) receives the size required. */
+int dock_autotune_report(char* buf, int32_t cap, int32_t* needed);
+int dock_autotune_clear(void);
+
 /* Advances every trajectory by n_steps more MC steps (resume). */
 int dock_run_advance(dock_run_t r, int32_t n_steps, void* stream);
 

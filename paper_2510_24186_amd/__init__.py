@@ -5,3 +5,4 @@ include/dock.h); `binding` marshals arguments with the ABI's names.
 """
 from .binding import *  # noqa: F401,F403
 from .binding import lib, DockError, Pocket, Ligands, Run  # noqa: F401
+from .autograd import DockScoreFn, dock_score  # noqa: F401

@@ -81,9 +81,15 @@ _sig("dock_ligands_count", C.c_int, _p, C.POINTER(_i32), C.POINTER(_i32), C.POIN
      C.POINTER(C.c_int64))
 _sig("dock_free_ligands", C.c_int, _p)
 _sig("dock_score_grad", C.c_int, _p, _i32, _p, C.c_int64, _p, _p, _i32, _p, _p, _p, _i32, _p)
+_sig("dock_score_terms", C.c_int, _p, _i32, _p, C.c_int64, _p, _p, _i32, _p, _i32, _p, _p, _p, _p)
+_sig("dock_score_adjoint", C.c_int, _p, _i32, _p, C.c_int64, _p, _p, _i32, _p, _i32, _p, _p, _p, _p, _p,
+     _p, _p, _p)
 _sig("dock_sample_params_default", None, C.POINTER(SampleParams))
 _sig("dock_sample", C.c_int, _p, _i32, _p, C.POINTER(SampleParams), _p, C.POINTER(_p))
 _sig("dock_run_advance", C.c_int, _p, _i32, _p)
+_sig("dock_autotune", C.c_int, _p, _i32, _p, C.POINTER(SampleParams), _i32, _p)
+_sig("dock_autotune_report", C.c_int, C.c_char_p, _i32, C.POINTER(_i32))
+_sig("dock_autotune_clear", C.c_int)
 _sig("dock_run_view_get", C.c_int, _p, C.POINTER(RunView))
 _sig("dock_run_copy_state", C.c_int, _p, _p, _p, _p, _p, _p, _p, _p)
 _sig("dock_run_set_state", C.c_int, _p, _p, _p, _p, _p, _i32, _p)
@@ -305,6 +311,56 @@ def dock_score_grad(pockets, L, pose_lig, q, want_grad=True, want_xyz=False, str
     return E, g, xyz
 
 
+# ------------------------------------------------------------------ differentiable form
+
+def _ptr_array(ts, n):
+    if ts is None:
+        return None
+    return (_p * n)(*[None if t is None else t.data_ptr() for t in ts])
+
+
+def _terms_common(pockets, L, pose_lig, q, xyz, G, w):
+    import torch
+    if isinstance(pockets, Pocket):
+        pockets = [pockets]
+    arr, npk = _pocket_array(pockets)
+    pose_lig = _cuda_check(pose_lig, torch.int32, "pose_lig")
+    q = _cuda_check(q, torch.float32, "q")
+    xyz = _cuda_check(xyz, torch.float32, "xyz")
+    w = _cuda_check(w, torch.float32, "w")
+    if G is not None:
+        G = [None if t is None else _cuda_check(t, torch.float32, "G") for t in G]
+    return pockets, arr, npk, pose_lig, q, xyz, G, w
+
+
+def dock_score_terms(pockets, L, pose_lig, w, q=None, xyz=None, G=None, stream=None):
+    """E of each pose with caller maps G (list per pocket, None = kept maps)
+    and weights w [n_pockets, K]."""
+    import torch
+    pockets, arr, npk, pose_lig, q, xyz, G, w = _terms_common(pockets, L, pose_lig, q, xyz, G, w)
+    n = pose_lig.shape[0]
+    E = torch.empty(n, dtype=torch.float32, device=pose_lig.device)
+    qs = q.shape[1] if q is not None else 0
+    xs = 3 * L.max_atoms
+    _check(lib.dock_score_terms(arr, npk, L.handle, n, _dptr(pose_lig), _dptr(q), qs, _dptr(xyz), xs,
+                                _ptr_array(G, npk), _dptr(w), _dptr(E), _stream(stream)))
+    return E
+
+
+def dock_score_adjoint(pockets, L, pose_lig, w, dLdE, q=None, xyz=None, G=None, dLdG=None, dLdw=None,
+                       dLdq=None, dLdx=None, stream=None):
+    """Accumulates (+=) gradients of sum_p dLdE[p] E_p into the given buffers."""
+    import torch
+    pockets, arr, npk, pose_lig, q, xyz, G, w = _terms_common(pockets, L, pose_lig, q, xyz, G, w)
+    dLdE = _cuda_check(dLdE, torch.float32, "dLdE")
+    n = pose_lig.shape[0]
+    qs = q.shape[1] if q is not None else 0
+    xs = 3 * L.max_atoms
+    _check(lib.dock_score_adjoint(arr, npk, L.handle, n, _dptr(pose_lig), _dptr(q), qs, _dptr(xyz), xs,
+                                  _ptr_array(G, npk), _dptr(w), _dptr(dLdE), _ptr_array(dLdG, npk),
+                                  _dptr(dLdw), _dptr(dLdq), _dptr(dLdx), _stream(stream)))
+
+
 # ------------------------------------------------------------------ sampling
 
 class Run:
@@ -346,6 +402,28 @@ def dock_sample(pockets, L, stream=None, **params):
     h = _p()
     _check(lib.dock_sample(arr, npk, L.handle, C.byref(p), _stream(stream), C.byref(h)))
     return Run(h, L, p.n_traj)
+
+
+def dock_autotune(pockets, L, trial_steps=2, stream=None, **params):
+    """Tune group width and block size per lane configuration; returns the cache."""
+    import json
+    p = sample_params(**params)
+    arr, npk = _pocket_array(pockets)
+    _check(lib.dock_autotune(arr, npk, L.handle, C.byref(p), int(trial_steps), _stream(stream)))
+    return dock_autotune_report()
+
+
+def dock_autotune_report():
+    import json
+    need = _i32()
+    _check(lib.dock_autotune_report(None, 0, C.byref(need)))
+    buf = C.create_string_buffer(need.value)
+    _check(lib.dock_autotune_report(buf, need.value, C.byref(need)))
+    return json.loads(buf.value.decode())
+
+
+def dock_autotune_clear():
+    _check(lib.dock_autotune_clear())
 
 
 def dock_run_advance(run, n_steps, stream=None):

@@ -11,6 +11,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "dock_device.h"
@@ -128,6 +129,29 @@ static LaneCfg lane_cfg(const LigDev& lg, int force_lpp) {
   if (c.apl == 2) c.lpp = 64;
   if (force_lpp > c.lpp && c.apl == 1) c.lpp = force_lpp;
   return c;
+}
+
+// Autotuner choices per natural lane configuration (lpp, apl): the group
+// width and block size that measured fastest, process-wide, per device arch.
+struct TuneChoice {
+  int lpp, block;
+  float ms;
+};
+static std::mutex g_tune_mu;
+static std::map<std::tuple<std::string, int, int>, TuneChoice> g_tune;
+
+static std::string device_arch() {
+  static std::mutex mu;
+  static std::map<int, std::string> names;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = names.find(dev);
+  if (it != names.end()) return it->second;
+  hipDeviceProp_t prop;
+  std::string name = hipGetDeviceProperties(&prop, dev) == hipSuccess ? std::string(prop.gcnArchName) : "unknown";
+  names[dev] = name;
+  return name;
 }
 
 extern "C" {
@@ -343,10 +367,14 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
       g.box_min[c] = H.box_min[c];
       g.box_max[c] = H.box_max[c];
     }
+    // coordinates relative to the root centroid c0 (FP64 difference, rounded
+    // once): the rotation then acts on vectors of ligand size, not on
+    // absolute positions, which keeps FP32 forward kinematics accurate
     for (int na = 0; na < H.n_atoms; ++na) {
       const int a = H.dfs_atom[na];
       const int bits = int(H.type[a]) | (H.frag_new[H.atom_frag[a]] << 8) | (a << 16);
-      float4 v = make_float4(H.x0[3 * a], H.x0[3 * a + 1], H.x0[3 * a + 2], 0.f);
+      float4 v = make_float4(float(double(H.x0[3 * a]) - H.c0[0]), float(double(H.x0[3 * a + 1]) - H.c0[1]),
+                             float(double(H.x0[3 * a + 2]) - H.c0[2]), 0.f);
       std::memcpy(&v.w, &bits, 4);
       atoms.push_back(v);
     }
@@ -369,7 +397,7 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
         const double inv = 1.0 / std::sqrt(n2);
         for (int c = 0; c < 3; ++c) {
           fd.u[c] = float(u[c] * inv);
-          fd.xb[c] = H.x0[3 * b + c];
+          fd.xb[c] = float(double(H.x0[3 * b + c]) - H.c0[c]);
         }
         fd.parent = H.frag_new[H.frag_parent[f]];
         fd.dof = 6 + k;
@@ -562,6 +590,85 @@ int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligand
   a.max_pairs = L->max_pairs;
   HIP_TRY(launch_score(a, lpp, apl, reinterpret_cast<hipStream_t>(stream)));
   return DOCK_OK;
+}
+
+// ================================================================ differentiable form
+
+static int terms_call(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L, int64_t n_poses,
+                      const int32_t* pose_lig, const float* q, int32_t q_stride, const float* xyz,
+                      int32_t xyz_stride, const float* const* G, const float* w, float* E,
+                      const float* dLdE, float* const* dLdG, float* dLdw, float* dLdq, float* dLdx,
+                      void* stream) {
+  if (!L) return fail(DOCK_E_ARG, "null ligands");
+  int rc = check_pockets(pockets, n_pockets, L);
+  if (rc) return rc;
+  if (n_pockets > kMaxDiffPockets) return fail(DOCK_E_LIMIT, "more than 16 pockets in one differentiable call");
+  const int K = pockets[0]->dev.n_terms;
+  for (int i = 1; i < n_pockets; ++i)
+    if (pockets[i]->dev.n_terms != K) return fail(DOCK_E_ARG, "pockets of one call must share a preset");
+  if (n_poses < 0) return fail(DOCK_E_ARG, "negative n_poses");
+  if (n_poses == 0) return DOCK_OK;
+  if (!pose_lig || !w) return fail(DOCK_E_ARG, "null pose_lig or weights");
+  if ((q == nullptr) == (xyz == nullptr)) return fail(DOCK_E_ARG, "give exactly one of q and xyz");
+  if (q && q_stride < 6 + L->max_tors) return fail(DOCK_E_ARG, "q_stride < 6 + max torsions");
+  if ((xyz || dLdx) && xyz_stride < 3 * L->max_atoms) return fail(DOCK_E_ARG, "xyz_stride < 3 * max atoms");
+  if (xyz && dLdq) return fail(DOCK_E_ARG, "dLdq needs poses given as DOFs");
+  if (dLdq && q_stride < 6 + L->max_tors) return fail(DOCK_E_ARG, "q_stride < 6 + max torsions");
+  const PocketDev* tab = nullptr;
+  rc = pocket_table(pockets, n_pockets, &tab);
+  if (rc) return rc;
+  TermsArgs a{};
+  for (int i = 0; i < n_pockets; ++i) {
+    const float* gi = (G && G[i]) ? G[i] : pockets[i]->d_G;
+    if (!gi) return fail(DOCK_E_ARG, "no per-term maps for pocket " + std::to_string(i));
+    a.G[i] = gi;
+    a.dLdG[i] = dLdG ? dLdG[i] : nullptr;
+  }
+  int lpp = 16, apl = 1;
+  for (const LigDev& g : L->h_ligs) {
+    LaneCfg c = lane_cfg(g, 0);
+    lpp = std::max(lpp, c.lpp);
+    apl = std::max(apl, c.apl);
+  }
+  if (apl == 2) lpp = 64;
+  if (score_lds_bytes(lpp, apl, L->max_pairs) > 64 * 1024)
+    return fail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
+  a.L = L->arrays();
+  a.pockets = tab;
+  a.n_ligands = L->n;
+  a.n_pockets = n_pockets;
+  a.n_poses = n_poses;
+  a.pose_lig = pose_lig;
+  a.q = q;
+  a.q_stride = q_stride;
+  a.xyz = xyz;
+  a.xyz_stride = xyz_stride;
+  a.w = w;
+  a.E = E;
+  a.dLdE = dLdE;
+  a.dLdw = dLdw;
+  a.dLdq = dLdq;
+  a.dLdx = dLdx;
+  a.max_pairs = L->max_pairs;
+  HIP_TRY(launch_terms(a, lpp, apl, K, reinterpret_cast<hipStream_t>(stream)));
+  return DOCK_OK;
+}
+
+int dock_score_terms(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L, int64_t n_poses,
+                     const int32_t* pose_lig, const float* q, int32_t q_stride, const float* xyz,
+                     int32_t xyz_stride, const float* const* G, const float* w, float* E, void* stream) {
+  if (!E) return fail(DOCK_E_ARG, "null E");
+  return terms_call(pockets, n_pockets, L, n_poses, pose_lig, q, q_stride, xyz, xyz_stride, G, w, E, nullptr,
+                    nullptr, nullptr, nullptr, nullptr, stream);
+}
+
+int dock_score_adjoint(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L, int64_t n_poses,
+                       const int32_t* pose_lig, const float* q, int32_t q_stride, const float* xyz,
+                       int32_t xyz_stride, const float* const* G, const float* w, const float* dLdE,
+                       float* const* dLdG, float* dLdw, float* dLdq, float* dLdx, void* stream) {
+  if (!dLdE) return fail(DOCK_E_ARG, "null dLdE");
+  return terms_call(pockets, n_pockets, L, n_poses, pose_lig, q, q_stride, xyz, xyz_stride, G, w, nullptr, dLdE,
+                    dLdG, dLdw, dLdq, dLdx, stream);
 }
 
 // ================================================================ sampling
@@ -812,8 +919,15 @@ static int check_params(const dock_sample_params* p) {
   return DOCK_OK;
 }
 
-int dock_sample(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
-                const dock_sample_params* p, void* stream, dock_run_t* out) {
+// Plan overrides used by the autotuner: a forced (lpp, block) for one natural
+// lane configuration, and the subset of ligands that get work items.
+struct PlanOverride {
+  int nat_lpp = 0, nat_apl = 0, lpp = 0, block = 0;
+  const std::vector<char>* subset = nullptr;
+};
+
+static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
+                      const dock_sample_params* p, void* stream, dock_run_t* out, const PlanOverride* ov) {
   if (!L || !out) return fail(DOCK_E_ARG, "null argument");
   int rc = check_pockets(pockets, n_pockets, L);
   if (rc) return rc;
@@ -843,12 +957,26 @@ int dock_sample(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t 
   int dev = 0, n_cu = 256;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n_cu = 256;
-  const int block = 256;
-  std::map<std::pair<int, int>, int> bidx;
+  std::map<std::tuple<int, int, int>, int> bidx;
   r->lig_bucket.resize(r->n_lig);
+  const std::string arch = device_arch();
   for (int l = 0; l < r->n_lig; ++l) {
-    const LaneCfg c = lane_cfg(L->h_ligs[l], p->lanes_per_pose);
-    auto key = std::make_pair(c.lpp, c.apl);
+    LaneCfg c = lane_cfg(L->h_ligs[l], p->lanes_per_pose);
+    int block = 256;
+    if (ov && ov->lpp) {
+      if (c.lpp == ov->nat_lpp && c.apl == ov->nat_apl) {
+        c.lpp = ov->lpp;
+        block = ov->block;
+      }
+    } else if (p->lanes_per_pose == 0) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto t = g_tune.find(std::make_tuple(arch, c.lpp, c.apl));
+      if (t != g_tune.end()) {
+        c.lpp = t->second.lpp;
+        block = t->second.block;
+      }
+    }
+    auto key = std::make_tuple(c.lpp, c.apl, block);
     auto it = bidx.find(key);
     if (it == bidx.end()) {
       Bucket B;
@@ -871,7 +999,8 @@ int dock_sample(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t 
       const Bucket& B = r->buckets[r->lig_bucket[l]];
       const int gpb = B.block / B.lpp;
       r->lig_item_off[l] = int(items.size());
-      for (int t0 = 0; t0 < r->T; t0 += gpb) items.push_back(make_int2(l, t0));
+      if (!(ov && ov->subset && !(*ov->subset)[l]))
+        for (int t0 = 0; t0 < r->T; t0 += gpb) items.push_back(make_int2(l, t0));
       r->lig_n_items[l] = int(items.size()) - r->lig_item_off[l];
     }
   } else {
@@ -884,8 +1013,10 @@ int dock_sample(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t 
         return gx.n_pairs + 4 * gx.n_atoms > gy.n_pairs + 4 * gy.n_atoms;
       });
       B.item_off = int(items.size());
-      for (int l : ligs)
+      for (int l : ligs) {
+        if (ov && ov->subset && !(*ov->subset)[l]) continue;
         for (int t0 = 0; t0 < r->T; t0 += gpb) items.push_back(make_int2(l, t0));
+      }
       B.n_items = int(items.size()) - B.item_off;
       const size_t lds = sample_lds_bytes(B.lpp, B.apl, B.block, B.max_pairs);
       if (lds > 64 * 1024) return bail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
@@ -932,6 +1063,99 @@ int dock_sample(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t 
     return fail(rc, m);
   }
   *out = r;
+  return DOCK_OK;
+}
+
+int dock_sample(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
+                const dock_sample_params* p, void* stream, dock_run_t* out) {
+  return create_run(pockets, n_pockets, L, p, stream, out, nullptr);
+}
+
+int dock_autotune(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
+                  const dock_sample_params* p, int32_t trial_steps, void* stream) {
+  if (!L || !p) return fail(DOCK_E_ARG, "null argument");
+  if (trial_steps < 1) return fail(DOCK_E_ARG, "trial_steps must be >= 1");
+  int rc = check_pockets(pockets, n_pockets, L);
+  if (rc) return rc;
+  rc = check_params(p);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // natural lane configurations present in L
+  std::map<std::pair<int, int>, std::vector<char>> nat;
+  for (int l = 0; l < L->n; ++l) {
+    const LaneCfg c = lane_cfg(L->h_ligs[l], 0);
+    auto& m = nat[std::make_pair(c.lpp, c.apl)];
+    if (m.empty()) m.assign(L->n, 0);
+    m[l] = 1;
+  }
+  dock_sample_params q = *p;
+  q.n_steps = 0;
+  q.form = DOCK_FORM_BATCHED;
+  q.use_graph = 0;
+  q.steps_per_launch = 0;
+  q.record_trace = 0;
+  q.lanes_per_pose = 0;
+  const std::string arch = device_arch();
+  for (auto& kv : nat) {
+    const int lpp0 = kv.first.first, apl = kv.first.second;
+    std::vector<int> widths{lpp0};
+    if (apl == 1 && lpp0 < 64) widths.push_back(lpp0 * 2);
+    TuneChoice best{lpp0, 256, 1e30f};
+    for (int lpp : widths)
+      for (int block : {64, 128, 256}) {
+        if (block < lpp) continue;
+        PlanOverride ov;
+        ov.nat_lpp = lpp0;
+        ov.nat_apl = apl;
+        ov.lpp = lpp;
+        ov.block = block;
+        ov.subset = &kv.second;
+        dock_run_t run = nullptr;
+        rc = create_run(pockets, n_pockets, L, &q, stream, &run, &ov);
+        if (rc) return rc;
+        rc = dock_run_advance(run, trial_steps, stream);
+        float ms = 0.f;
+        if (rc == DOCK_OK) rc = dock_run_kernel_ms(run, &ms);
+        dock_free_run(run);
+        if (rc) return rc;
+        if (ms < best.ms) best = TuneChoice{lpp, block, ms};
+      }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(arch, lpp0, apl)] = best;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return DOCK_OK;
+}
+
+int dock_autotune_report(char* buf, int32_t cap, int32_t* needed) {
+  std::string out = "[";
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    bool firstv = true;
+    for (auto& kv : g_tune) {
+      if (!firstv) out += ", ";
+      firstv = false;
+      char line[256];
+      std::snprintf(line, sizeof line,
+                    "{\"arch\": \"%s\", \"lanes\": %d, \"atoms_per_lane\": %d, \"chosen_lanes\": %d, "
+                    "\"block\": %d, \"trial_ms\": %.4f}",
+                    std::get<0>(kv.first).c_str(), std::get<1>(kv.first), std::get<2>(kv.first),
+                    kv.second.lpp, kv.second.block, kv.second.ms);
+      out += line;
+    }
+  }
+  out += "]";
+  if (needed) *needed = int32_t(out.size() + 1);
+  if (buf && cap > 0) {
+    std::strncpy(buf, out.c_str(), size_t(cap) - 1);
+    buf[cap - 1] = 0;
+  }
+  return DOCK_OK;
+}
+
+int dock_autotune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
   return DOCK_OK;
 }
 

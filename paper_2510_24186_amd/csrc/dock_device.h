@@ -50,16 +50,65 @@ DK_INLINE uint32_t pick4(uint4 w, int i) {
   return i == 0 ? w.x : (i == 1 ? w.y : (i == 2 ? w.z : w.w));
 }
 
-// ------------------------------------------------------------------ shuffles
+// ------------------------------------------------------------------ cross-lane
+// Groups of W lanes (W = 16, 32, 64) inside one wavefront.  ds_bpermute
+// takes a byte address; when several values come from the same source lane
+// the address is computed once (bp_addr) and reused.
 template <int W>
-DK_INLINE float shfl(float v, int src) { return __shfl(v, src, W); }
+DK_INLINE int bp_addr(int src) {
+  return int((__lane_id() & ~unsigned(W - 1)) + unsigned(src)) << 2;
+}
+DK_INLINE float bp(int addr, float v) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+DK_INLINE int bp(int addr, int v) { return __builtin_amdgcn_ds_bpermute(addr, v); }
 template <int W>
-DK_INLINE int shfl(int v, int src) { return __shfl(v, src, W); }
+DK_INLINE float shfl(float v, int src) { return bp(bp_addr<W>(src), v); }
+template <int W>
+DK_INLINE int shfl(int v, int src) { return bp(bp_addr<W>(src), v); }
+
+// DPP controls (GFX9 encoding)
+constexpr int kDppQuadXor1 = 0xB1;    // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;    // quad_perm [2,3,0,1]
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppRowShr2 = 0x112;
+constexpr int kDppRowShr4 = 0x114;
+constexpr int kDppRowShr8 = 0x118;
+constexpr int kDppRowMirror = 0x140;      // lane i <-> 15 - i within a row
+constexpr int kDppRowHalfMirror = 0x141;  // lane i <-> 7 - i within a half row
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+template <int CTRL, int ROW_MASK = 0xf>
+DK_INLINE float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+
+// Sum over the group.  Every step adds a lane's value to its partner's, and
+// the partner does the same with the operands swapped, so all lanes end with
+// bitwise-identical sums (MC decisions taken from them are uniform).
 template <int W>
 DK_INLINE float group_sum(float v) {
-#pragma unroll
-  for (int m = W / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, W);
-  return v;  // identical on every lane (each step adds two commuted operands)
+  v += dpp<kDppQuadXor1>(v);
+  v += dpp<kDppQuadXor2>(v);
+  v += dpp<kDppRowHalfMirror>(v);
+  v += dpp<kDppRowMirror>(v);
+  if (W >= 32) v += __shfl_xor(v, 16, W);
+  if (W >= 64) v += __shfl_xor(v, 32, W);
+  return v;
+}
+
+// Inclusive prefix sum over the group (Hillis-Steele within 16-lane rows,
+// then row totals broadcast to the following rows).
+template <int W>
+DK_INLINE float group_scan(float v) {
+  v += dpp<kDppRowShr1>(v);
+  v += dpp<kDppRowShr2>(v);
+  v += dpp<kDppRowShr4>(v);
+  v += dpp<kDppRowShr8>(v);
+  if (W >= 32) v += dpp<kDppRowBcast15, 0xa>(v);
+  if (W >= 64) v += dpp<kDppRowBcast31, 0xc>(v);
+  return v;
 }
 
 // ------------------------------------------------------------------ terms
@@ -71,6 +120,12 @@ struct PairRec {
   float rsum;
 };
 
+// exp(x) on the hardware exp2 (v_exp_f32): callers pass x * log2(e) already
+// folded into their constants.  Relative error ~1e-6 for the Gaussian
+// arguments used here (|x| < 40).
+DK_INLINE float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
+constexpr float kLog2e = 1.4426950408889634f;
+
 // Weighted TRIDS terms (Methods: E_long, E_clash, E_Hbond) at distance d
 // (d2 = d*d): energy and dE/dd.
 DK_INLINE void trids_pair(float d2, float d, float rsum, uint32_t flags, const float* w, float& e,
@@ -79,7 +134,7 @@ DK_INLINE void trids_pair(float d2, float d, float rsum, uint32_t flags, const f
   de = 0.f;
   if (d2 < 100.0f) {
     const float s = d - rsum - 3.0f;
-    const float ex = expf(-0.25f * s * s);
+    const float ex = exp2_hw(s * s * (-0.25f * kLog2e));
     e -= w[0] * ex;
     de += w[0] * 0.5f * s * ex;
   }
@@ -92,7 +147,7 @@ DK_INLINE void trids_pair(float d2, float d, float rsum, uint32_t flags, const f
   }
   if (hb && d2 < 3.4f * 3.4f) {
     const float t = d - 2.88f;
-    const float ex = expf(-t * t * (1.0f / 0.18f));
+    const float ex = exp2_hw(t * t * (-kLog2e / 0.18f));
     e -= w[2] * ex;
     de += w[2] * ex * t * (2.0f / 0.18f);
   }
@@ -105,11 +160,11 @@ DK_INLINE void vina_pair(float d2, float d, float rsum, uint32_t flags, const fl
   de = 0.f;
   if (!(d2 < 64.0f)) return;
   const float s = d - rsum;
-  const float g1 = expf(-4.0f * s * s);
+  const float g1 = exp2_hw(s * s * (-4.0f * kLog2e));
   e += w[0] * g1;
   de -= w[0] * 8.0f * s * g1;
   const float t = s - 3.0f;
-  const float g2 = expf(-0.25f * t * t);
+  const float g2 = exp2_hw(t * t * (-0.25f * kLog2e));
   e += w[1] * g2;
   de -= w[1] * 0.5f * t * g2;
   if (s < 0.f) {
@@ -130,6 +185,66 @@ DK_INLINE void vina_pair(float d2, float d, float rsum, uint32_t flags, const fl
     } else if (s < 0.f) {
       e -= w[4] * s * (1.0f / 0.7f);
       de -= w[4] * (1.0f / 0.7f);
+    }
+  }
+}
+
+// Unweighted per-term values and d/dd of a ligand-internal pair (FP32, cutoff
+// decisions on the FP32 squared distance).  Order as the presets' weights.
+template <int K>
+DK_INLINE void pair_terms_f32(float d2, float d, float rsum, uint32_t flags, float (&v)[K],
+                              float (&dv)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = dv[k] = 0.f;
+  if (K == 3) {
+    if (d2 < 100.0f) {
+      const float s = d - rsum - 3.0f;
+      const float ex = expf(-0.25f * s * s);
+      v[0] = -ex;
+      dv[0] = 0.5f * s * ex;
+    }
+    const bool hb = flags & 1u;
+    const float dc = hb ? 2.6f : rsum;
+    if (d2 < dc * dc) {
+      const float dd = fmaxf(d, 0.1f);
+      v[1] = -logf(dd / dc);
+      dv[1] = d > 0.1f ? -1.0f / dd : 0.f;
+    }
+    if (hb && d2 < 3.4f * 3.4f) {
+      const float t = d - 2.88f;
+      const float ex = expf(-t * t * (1.0f / 0.18f));
+      v[2] = -ex;
+      dv[2] = ex * t * (2.0f / 0.18f);
+    }
+  } else {
+    if (!(d2 < 64.0f)) return;
+    const float s = d - rsum;
+    const float g1 = expf(-4.0f * s * s);
+    v[0] = g1;
+    dv[0] = -8.0f * s * g1;
+    const float t = s - 3.0f;
+    const float g2 = expf(-0.25f * t * t);
+    v[1] = g2;
+    dv[1] = -0.5f * t * g2;
+    if (s < 0.f) {
+      v[2] = s * s;
+      dv[2] = 2.0f * s;
+    }
+    if (flags & 2u) {
+      if (s < 0.5f) {
+        v[3] = 1.0f;
+      } else if (s < 1.5f) {
+        v[3] = 1.5f - s;
+        dv[3] = -1.0f;
+      }
+    }
+    if (flags & 1u) {
+      if (s < -0.7f) {
+        v[4] = 1.0f;
+      } else if (s < 0.f) {
+        v[4] = -s * (1.0f / 0.7f);
+        dv[4] = -1.0f / 0.7f;
+      }
     }
   }
 }
@@ -221,7 +336,6 @@ DK_INLINE Trilerp trilerp(const float* __restrict__ M, const GridDev& g, float p
 template <int APL>
 struct LaneLig {
   int n_atoms, n_frags, n_dof, n_pairs, fk_rounds, preset;
-  float c0x, c0y, c0z;
   // atoms owned by this lane
   float ax[APL], ay[APL], az[APL];
   int atype[APL], afrag[APL], aorig[APL];
@@ -235,18 +349,15 @@ struct LaneLig {
 };
 
 template <int LPP, int APL>
-DK_INLINE void load_lane_lig(LaneLig<APL>& L, const LigDev& lg, const float4* __restrict__ atoms,
-                             const FragDev* __restrict__ frags, const TorsDev* __restrict__ tors,
-                             const PocketDev& pk, int r) {
+DK_INLINE void load_lane_lig(LaneLig<APL>& L, const LigDev& lg, const LigDev* __restrict__ lgp,
+                             const float4* __restrict__ atoms, const FragDev* __restrict__ frags,
+                             const TorsDev* __restrict__ tors, const PocketDev& pk, int r) {
   L.n_atoms = lg.n_atoms;
   L.n_frags = lg.n_frags;
   L.n_dof = lg.n_dof;
   L.n_pairs = lg.n_pairs;
   L.fk_rounds = lg.fk_rounds;
   L.preset = pk.preset;
-  L.c0x = lg.c0[0];
-  L.c0y = lg.c0[1];
-  L.c0z = lg.c0[2];
 #pragma unroll
   for (int s = 0; s < APL; ++s) {
     const int a = APL * r + s;
@@ -280,8 +391,9 @@ DK_INLINE void load_lane_lig(LaneLig<APL>& L, const LigDev& lg, const float4* __
   }
   L.tsb = L.tse = L.ta = L.tb = 0;
   if (r < 3) {
-    L.lo = lg.box_min[r];
-    L.hi = lg.box_max[r];
+    // lane-indexed: read from memory, not from the register copy `lg`
+    L.lo = lgp->box_min[r];
+    L.hi = lgp->box_max[r];
   } else {
     L.lo = -kPi;
     L.hi = kPi;
@@ -332,13 +444,14 @@ DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][
   float m[9], t[3];
   int anc = L.fparent;
   if (L.fparent < 0) {
-    // root (and idle lanes): world rotation R = Rz Ry Rx, t = T - R c0
+    // root (and idle lanes): world rotation R = Rz Ry Rx about c0, which is
+    // the origin of the stored coordinates, so the translation is T itself
     m[0] = ca * cb; m[1] = ca * sb * sg - sa * cg; m[2] = ca * sb * cg + sa * sg;
     m[3] = sa * cb; m[4] = sa * sb * sg + ca * cg; m[5] = sa * sb * cg - ca * sg;
     m[6] = -sb;     m[7] = cb * sg;                m[8] = cb * cg;
-    t[0] = Tx - (m[0] * L.c0x + m[1] * L.c0y + m[2] * L.c0z);
-    t[1] = Ty - (m[3] * L.c0x + m[4] * L.c0y + m[5] * L.c0z);
-    t[2] = Tz - (m[6] * L.c0x + m[7] * L.c0y + m[8] * L.c0z);
+    t[0] = Tx;
+    t[1] = Ty;
+    t[2] = Tz;
   } else {
     // Rodrigues rotation about u through xb by theta: y -> B y + (xb - B xb)
     float st, ct;
@@ -353,13 +466,13 @@ DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][
   }
   // pointer jumping: C_f <- C_anc o C_f until every fragment reaches the root
   for (int it = 0; it < L.fk_rounds; ++it) {
-    const int src = anc >= 0 ? anc : r;
+    const int ad = bp_addr<LPP>(anc >= 0 ? anc : r);
     float a[9], b[3];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) a[k] = shfl<LPP>(m[k], src);
+    for (int k = 0; k < 9; ++k) a[k] = bp(ad, m[k]);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) b[k] = shfl<LPP>(t[k], src);
-    const int anc2 = shfl<LPP>(anc, src);
+    for (int k = 0; k < 3; ++k) b[k] = bp(ad, t[k]);
+    const int anc2 = bp(ad, anc);
     if (anc >= 0) {
       float nm[9], nt[3];
 #pragma unroll
@@ -378,12 +491,12 @@ DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][
   }
 #pragma unroll
   for (int s = 0; s < APL; ++s) {
-    const int f = L.afrag[s];
+    const int ad = bp_addr<LPP>(L.afrag[s]);
     float a[9], b[3];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) a[k] = shfl<LPP>(m[k], f);
+    for (int k = 0; k < 9; ++k) a[k] = bp(ad, m[k]);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) b[k] = shfl<LPP>(t[k], f);
+    for (int k = 0; k < 3; ++k) b[k] = bp(ad, t[k]);
     x[s][0] = a[0] * L.ax[s] + a[1] * L.ay[s] + a[2] * L.az[s] + b[0];
     x[s][1] = a[3] * L.ax[s] + a[4] * L.ay[s] + a[5] * L.az[s] + b[1];
     x[s][2] = a[6] * L.ax[s] + a[7] * L.ay[s] + a[8] * L.az[s] + b[2];
@@ -392,6 +505,94 @@ DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][
   rg.Tx = Tx; rg.Ty = Ty; rg.Tz = Tz;
   rg.sa = sa; rg.ca = ca; rg.sb = sb; rg.cb = cb;
   return rg;
+}
+
+// Chain rule from atom gradients g (world frame) to the DOF held by lane r:
+//   dE/dT = sum g_i;  tau = sum (x_i - T) x g_i;
+//   dE/d(alpha, beta, gamma) = tau . (e_z, Rz e_y, Rz Ry e_x);
+//   dE/dtheta_k = u_k . sum_{i in subtree(k)} (x_i - x_{b_k}) x g_i.
+// Subtree sums are differences of one inclusive prefix scan over the atoms
+// (each torsion's subtree is a contiguous DFS range).  Reads the axis atoms'
+// coordinates from the slab.
+template <int LPP, int APL>
+DK_INLINE float chain_rule(const LaneLig<APL>& L, const Rigid& rg, const float (&x)[APL][3],
+                           const float (&g)[APL][3], const GroupSlab& S, int r) {
+  const float Tx = rg.Tx, Ty = rg.Ty, Tz = rg.Tz;
+  const float sa = rg.sa, ca = rg.ca, sb = rg.sb, cb = rg.cb;
+  float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float vs[APL][6];
+#pragma unroll
+  for (int s = 0; s < APL; ++s) {
+    const float rx = x[s][0] - Tx, ry = x[s][1] - Ty, rz = x[s][2] - Tz;
+    vs[s][0] = g[s][0];
+    vs[s][1] = g[s][1];
+    vs[s][2] = g[s][2];
+    vs[s][3] = ry * g[s][2] - rz * g[s][1];
+    vs[s][4] = rz * g[s][0] - rx * g[s][2];
+    vs[s][5] = rx * g[s][1] - ry * g[s][0];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] += vs[s][k];
+  }
+  // inclusive scan over lanes (lane r covers atoms up to APL*r + APL - 1)
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = group_scan<LPP>(v[k]);
+  // prefix at an atom boundary: P(end) = sum of atoms [0, end)
+  // lane holding atoms [APL*l, APL*l+APL): inclusive value v; with APL = 2,
+  // the partial up to its first atom is v - vs[1].
+  float vlast[6];
+  float vfirst[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    vlast[k] = v[k];
+    vfirst[k] = APL == 2 ? v[k] - vs[APL - 1][k] : v[k];
+  }
+  auto prefix = [&](int end, float* out) {
+    // all lanes call this with their own `end`; returns sum over [0, end)
+    const int a = end - 1;
+    const int ad = bp_addr<LPP>(a >= 0 ? a / APL : 0);
+    const bool first = APL == 2 && (a % APL) == 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float lv = bp(ad, vlast[k]);
+      const float fv = APL == 2 ? bp(ad, vfirst[k]) : lv;
+      out[k] = a < 0 ? 0.f : (first ? fv : lv);
+    }
+  };
+  float tot[6];
+  prefix(L.n_atoms, tot);
+  float pb[6], pe[6];
+  prefix(L.tsb, pb);
+  prefix(L.tse, pe);
+  // axis atoms of this lane's torsion
+  const float4 xa = S.xs[L.ta], xb = S.xs[L.tb];
+  // ---- gradient of this lane's DOF
+  float gq = 0.f;
+  if (r < 3) {
+    gq = tot[r];
+  } else if (r == 3) {
+    gq = tot[5];
+  } else if (r == 4) {
+    gq = -sa * tot[3] + ca * tot[4];
+  } else if (r == 5) {
+    gq = ca * cb * tot[3] + sa * cb * tot[4] - sb * tot[5];
+  } else if (r < L.n_dof) {
+    float Sg[3], St[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Sg[k] = pe[k] - pb[k];
+      St[k] = pe[3 + k] - pb[3 + k];
+    }
+    float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
+    const float inv = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+    ux *= inv; uy *= inv; uz *= inv;
+    const float bx = xb.x - Tx, by = xb.y - Ty, bz = xb.z - Tz;
+    // sum_sub (x_i - x_b) x g_i = St - r_b x Sg
+    const float cx = St[0] - (by * Sg[2] - bz * Sg[1]);
+    const float cy = St[1] - (bz * Sg[0] - bx * Sg[2]);
+    const float cz = St[2] - (bx * Sg[1] - by * Sg[0]);
+    gq = ux * cx + uy * cy + uz * cz;
+  }
+  return gq;
 }
 
 // One evaluation of E and dE/dq at the pose whose DOF r is held by lane r.
@@ -404,8 +605,6 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& L, float q, const float* __restr
   // ---- atoms: place, interpolate, publish coordinates to the slab
   float x[APL][3], g[APL][3];
   const Rigid rg = fk_place<LPP, APL>(L, q, r, x);
-  const float Tx = rg.Tx, Ty = rg.Ty, Tz = rg.Tz;
-  const float sa = rg.sa, ca = rg.ca, sb = rg.sb, cb = rg.cb;
   float e_lane = 0.f;
 #pragma unroll
   for (int s = 0; s < APL; ++s) {
@@ -434,15 +633,17 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& L, float q, const float* __restr
     const float4 xi = S.xs[i], xj = S.xs[j];
     const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
     const float d2 = dx * dx + dy * dy + dz * dz;
-    const float d = sqrtf(d2);
+    // 1/d from the hardware reciprocal square root; d = d2 / d
+    const float inv_d = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
+    const float d = d2 * inv_d;
     float e, de;
     if (L.preset == DOCK_PRESET_TRIDS)
       trids_pair(d2, d, pr.rsum, flags, L.w, e, de);
     else
       vina_pair(d2, d, pr.rsum, flags, L.w, e, de);
     e_lane += e;
-    if (de != 0.f && d > 0.f) {
-      const float c = de / d;
+    if (de != 0.f) {
+      const float c = de * inv_d;
       const float fx = c * dx, fy = c * dy, fz = c * dz;
       atomicAdd(&S.fx[i], fx);
       atomicAdd(&S.fy[i], fy);
@@ -453,9 +654,7 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& L, float q, const float* __restr
     }
   }
   wave_sync();
-  // ---- per-atom total gradient, torque terms and their prefix sums
-  float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  float vs[APL][6];
+  // ---- per-atom total gradient: add the intra-pair forces
 #pragma unroll
   for (int s = 0; s < APL; ++s) {
     const int atom = APL * r + s;
@@ -464,91 +663,123 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& L, float q, const float* __restr
       g[s][1] += S.fy[atom];
       g[s][2] += S.fz[atom];
     }
-    const float rx = x[s][0] - Tx, ry = x[s][1] - Ty, rz = x[s][2] - Tz;
-    vs[s][0] = g[s][0];
-    vs[s][1] = g[s][1];
-    vs[s][2] = g[s][2];
-    vs[s][3] = ry * g[s][2] - rz * g[s][1];
-    vs[s][4] = rz * g[s][0] - rx * g[s][2];
-    vs[s][5] = rx * g[s][1] - ry * g[s][0];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] += vs[s][k];
     if (WANT_X) {
       xo[s][0] = x[s][0]; xo[s][1] = x[s][1]; xo[s][2] = x[s][2];
       go[s][0] = g[s][0]; go[s][1] = g[s][1]; go[s][2] = g[s][2];
     }
   }
-  // inclusive scan over lanes (lane r covers atoms up to APL*r + APL - 1)
-#pragma unroll
-  for (int off = 1; off < LPP; off <<= 1) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const float o = __shfl_up(v[k], off, LPP);
-      if (r >= off) v[k] += o;
-    }
-  }
-  // prefix at an atom boundary: P(end) = sum of atoms [0, end)
-  // lane holding atoms [APL*l, APL*l+APL): inclusive value v; with APL = 2,
-  // the partial up to its first atom is v - vs[1].
-  float vlast[6];
-  float vfirst[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    vlast[k] = v[k];
-    vfirst[k] = APL == 2 ? v[k] - vs[APL - 1][k] : v[k];
-  }
-  auto prefix = [&](int end, float* out) {
-    // all lanes call this with their own `end`; returns sum over [0, end)
-    const int a = end - 1;
-    const int l = a >= 0 ? a / APL : 0;
-    const bool first = APL == 2 && (a % APL) == 0;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const float lv = shfl<LPP>(vlast[k], l);
-      const float fv = shfl<LPP>(vfirst[k], l);
-      out[k] = a < 0 ? 0.f : (first ? fv : lv);
-    }
-  };
-  float tot[6];
-  prefix(L.n_atoms, tot);
-  float pb[6], pe[6];
-  prefix(L.tsb, pb);
-  prefix(L.tse, pe);
-  // axis atoms of this lane's torsion
-  const float4 xa = S.xs[L.ta], xb = S.xs[L.tb];
-  // ---- energy
   EvalOut out;
   out.E = group_sum<LPP>(e_lane);
-  // ---- gradient of this lane's DOF
-  float gq = 0.f;
-  if (r < 3) {
-    gq = tot[r];
-  } else if (r == 3) {
-    gq = tot[5];
-  } else if (r == 4) {
-    gq = -sa * tot[3] + ca * tot[4];
-  } else if (r == 5) {
-    gq = ca * cb * tot[3] + sa * cb * tot[4] - sb * tot[5];
-  } else if (r < L.n_dof) {
-    float Sg[3], St[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      Sg[k] = pe[k] - pb[k];
-      St[k] = pe[3 + k] - pb[3 + k];
-    }
-    float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
-    const float inv = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
-    ux *= inv; uy *= inv; uz *= inv;
-    const float bx = xb.x - Tx, by = xb.y - Ty, bz = xb.z - Tz;
-    // sum_sub (x_i - x_b) x g_i = St - r_b x Sg
-    const float cx = St[0] - (by * Sg[2] - bz * Sg[1]);
-    const float cy = St[1] - (bz * Sg[0] - bx * Sg[2]);
-    const float cz = St[2] - (bx * Sg[1] - by * Sg[0]);
-    gq = ux * cx + uy * cy + uz * cz;
-  }
-  out.g = gq;
+  out.g = chain_rule<LPP, APL>(L, rg, x, g, S, r);
   wave_sync();  // slab reuse by the next evaluation
   return out;
+}
+
+// Differentiable form: the score over per-term maps G[t][k] with weights w
+// (E = sum_k w_k (sum_i trilerp(G[t_i][k], x_i) + sum_pairs phi_k) + E_out),
+// optionally scattering dL/dG for dL/dE = dLdE.  Atom positions come from FK
+// of q (XIN = false) or are given (XIN = true).  Leaves per-atom gradients in
+// g, per-term sums (reduced over the group) in ek, and returns E.
+template <int LPP, int APL, int K, bool XIN>
+DK_INLINE float eval_terms(const LaneLig<APL>& L, float q, float (&x)[APL][3], float (&g)[APL][3],
+                           Rigid& rg, const float* __restrict__ G, const GridDev& grid,
+                           const float (&w)[K], const PairRec* __restrict__ pairs, const GroupSlab& S,
+                           int r, float dLdE, float* __restrict__ dLdG, float (&ek)[K]) {
+  if (!XIN) rg = fk_place<LPP, APL>(L, q, r, x);
+  const size_t nxyz = size_t(grid.dims[0]) * grid.dims[1] * grid.dims[2];
+  const int nx = grid.dims[0], nxy = grid.dims[0] * grid.dims[1];
+  float el[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) el[k] = 0.f;
+  float eout = 0.f;
+#pragma unroll
+  for (int s = 0; s < APL; ++s) {
+    const int atom = APL * r + s;
+    g[s][0] = g[s][1] = g[s][2] = 0.f;
+    if (atom < L.n_atoms) {
+      const float* base = G + size_t(L.atype[s]) * K * nxyz;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const Trilerp tl = trilerp(base + size_t(k) * nxyz, grid, x[s][0], x[s][1], x[s][2]);
+        el[k] += tl.v;
+        if (k == 0) eout += tl.eout;  // the out-of-box penalty is the same for every term
+        // trilerp() adds the out-of-box slope to its gradient; remove it from
+        // every term and add it once below
+        const float px = x[s][0], py = x[s][1], pz = x[s][2];
+        const float sx = px > grid.hi[0] ? kOutK : (px < grid.origin[0] ? -kOutK : 0.f);
+        const float sy = py > grid.hi[1] ? kOutK : (py < grid.origin[1] ? -kOutK : 0.f);
+        const float sz = pz > grid.hi[2] ? kOutK : (pz < grid.origin[2] ? -kOutK : 0.f);
+        g[s][0] += w[k] * (tl.gx - sx);
+        g[s][1] += w[k] * (tl.gy - sy);
+        g[s][2] += w[k] * (tl.gz - sz);
+        if (k == K - 1) {
+          g[s][0] += sx;
+          g[s][1] += sy;
+          g[s][2] += sz;
+        }
+        if (dLdG) {
+          float* d = dLdG + size_t(L.atype[s] * K + k) * nxyz + tl.base;
+          const float c = dLdE * w[k];
+          const float fx = tl.fx, fy = tl.fy, fz = tl.fz;
+          atomicAdd(d, c * (1.f - fx) * (1.f - fy) * (1.f - fz));
+          atomicAdd(d + 1, c * fx * (1.f - fy) * (1.f - fz));
+          atomicAdd(d + nx, c * (1.f - fx) * fy * (1.f - fz));
+          atomicAdd(d + nx + 1, c * fx * fy * (1.f - fz));
+          atomicAdd(d + nxy, c * (1.f - fx) * (1.f - fy) * fz);
+          atomicAdd(d + nxy + 1, c * fx * (1.f - fy) * fz);
+          atomicAdd(d + nxy + nx, c * (1.f - fx) * fy * fz);
+          atomicAdd(d + nxy + nx + 1, c * fx * fy * fz);
+        }
+      }
+      S.xs[atom] = make_float4(x[s][0], x[s][1], x[s][2], 0.f);
+      S.fx[atom] = 0.f;
+      S.fy[atom] = 0.f;
+      S.fz[atom] = 0.f;
+    }
+  }
+  wave_sync();
+  for (int p = r; p < L.n_pairs; p += LPP) {
+    const PairRec pr = pairs[p];
+    const int i = pr.w & 0xff, j = (pr.w >> 8) & 0xff;
+    const float4 xi = S.xs[i], xj = S.xs[j];
+    const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+    const float d2 = dx * dx + dy * dy + dz * dz;
+    const float d = sqrtf(d2);
+    float v[K], dv[K];
+    pair_terms_f32<K>(d2, d, pr.rsum, pr.w >> 24, v, dv);
+    float de = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      el[k] += v[k];
+      de += w[k] * dv[k];
+    }
+    if (de != 0.f && d > 0.f) {
+      const float c = de / d;
+      atomicAdd(&S.fx[i], c * dx);
+      atomicAdd(&S.fy[i], c * dy);
+      atomicAdd(&S.fz[i], c * dz);
+      atomicAdd(&S.fx[j], -c * dx);
+      atomicAdd(&S.fy[j], -c * dy);
+      atomicAdd(&S.fz[j], -c * dz);
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int s = 0; s < APL; ++s) {
+    const int atom = APL * r + s;
+    if (atom < L.n_atoms) {
+      g[s][0] += S.fx[atom];
+      g[s][1] += S.fy[atom];
+      g[s][2] += S.fz[atom];
+    }
+  }
+  float E = group_sum<LPP>(eout);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    ek[k] = group_sum<LPP>(el[k]);
+    E += w[k] * ek[k];
+  }
+  return E;
 }
 
 DK_INLINE float wrap_angle(float a) { return a - kTwoPi * floorf((a + kPi) * kInvTwoPi); }

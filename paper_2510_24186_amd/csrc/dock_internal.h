@@ -32,6 +32,7 @@ struct alignas(16) LigDev {
 
 // Fragment record (DFS numbering).  Root: parent = -1, dof = -1.
 // A child turns about the input-frame axis through xb with unit direction u.
+// Atom coordinates and pivots are stored relative to the root centroid c0.
 struct alignas(16) FragDev {
   float u[3];
   float xb[3];

@@ -30,6 +30,29 @@ struct ScoreArgs {
   int max_pairs;
 };
 
+constexpr int kMaxDiffPockets = 16;
+
+struct TermsArgs {
+  LigandArrays L;
+  const PocketDev* pockets;  // grid geometry per pocket
+  int n_ligands, n_pockets;
+  long long n_poses;
+  const int* pose_lig;
+  const float* q;            // pose DOFs (coordinates mode: null)
+  int q_stride;
+  const float* xyz;          // world coordinates, caller atom order (DOF mode: null)
+  int xyz_stride;
+  const float* G[kMaxDiffPockets];   // per-term maps per pocket
+  const float* w;                    // device [n_pockets * K]
+  float* E;
+  const float* dLdE;                 // null: forward only
+  float* dLdG[kMaxDiffPockets];
+  float* dLdw;
+  float* dLdq;
+  float* dLdx;
+  int max_pairs;
+};
+
 struct SampleArgs {
   LigandArrays L;
   const PocketDev* pockets;
@@ -90,6 +113,7 @@ hipError_t launch_map_build(const MapArgs& a, hipStream_t s);
 hipError_t launch_score(const ScoreArgs& a, int lpp, int apl, hipStream_t s);
 hipError_t launch_sample(const SampleArgs& a, int lpp, int apl, int grid, int block, hipStream_t s);
 hipError_t launch_best(const BestArgs& a, hipStream_t s);
+hipError_t launch_terms(const TermsArgs& a, int lpp, int apl, int K, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, long long n, uint32_t* out,
                          hipStream_t s);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);

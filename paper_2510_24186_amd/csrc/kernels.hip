@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(64) score_kernel(ScoreArgs a) {
   const LigDev lg = a.L.ligs[lig];
   const PocketDev pk = a.pockets[lg.pocket];
   LaneLig<APL> L;
-  load_lane_lig<LPP, APL>(L, lg, a.L.atoms, a.L.frags, a.L.tors, pk, r);
+  load_lane_lig<LPP, APL>(L, lg, a.L.ligs + lig, a.L.atoms, a.L.frags, a.L.tors, pk, r);
   for (int p = r; p < lg.n_pairs; p += LPP) gp[p] = a.L.pairs[lg.pair_off + p];
   wave_sync();
   const float q = r < lg.n_dof ? a.q[pose * a.q_stride + r] : 0.f;
@@ -171,6 +171,101 @@ hipError_t launch_score(const ScoreArgs& a, int lpp, int apl, hipStream_t s) {
   else
     hipLaunchKernelGGL((score_kernel<64, 2>), dim3(blocks), dim3(64), lds, s, a);
   return hipGetLastError();
+}
+
+// ================================================================ differentiable form
+
+template <int LPP, int APL, int K, bool XIN>
+__global__ void __launch_bounds__(64) terms_kernel(TermsArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int GPB = 64 / LPP;
+  const int grp = threadIdx.x / LPP, r = threadIdx.x % LPP;
+  const long long pose = (long long)blockIdx.x * GPB + grp;
+  unsigned char* mine = smem + size_t(grp) * (pair_bytes(a.max_pairs) + slab_bytes(LPP, APL));
+  PairRec* gp = reinterpret_cast<PairRec*>(mine);
+  const GroupSlab S = make_slab<LPP, APL>(mine + pair_bytes(a.max_pairs));
+  if (pose >= a.n_poses) return;
+  const int lig = a.pose_lig[pose];
+  if (lig < 0 || lig >= a.n_ligands) {
+    if (r == 0 && a.E) a.E[pose] = __int_as_float(0x7fc00000);
+    return;
+  }
+  const LigDev lg = a.L.ligs[lig];
+  const int pi = lg.pocket;
+  const PocketDev pk = a.pockets[pi];
+  LaneLig<APL> L;
+  load_lane_lig<LPP, APL>(L, lg, a.L.ligs + lig, a.L.atoms, a.L.frags, a.L.tors, pk, r);
+  float w[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) w[k] = a.w[pi * K + k];
+  for (int p = r; p < lg.n_pairs; p += LPP) gp[p] = a.L.pairs[lg.pair_off + p];
+  wave_sync();
+  float q = 0.f;
+  float x[APL][3], g[APL][3], ek[K];
+  Rigid rg{};
+  if (XIN) {
+#pragma unroll
+    for (int s = 0; s < APL; ++s) {
+      const int atom = APL * r + s;
+      const float* src = a.xyz + pose * a.xyz_stride + 3 * L.aorig[s];
+      x[s][0] = atom < lg.n_atoms ? src[0] : 0.f;
+      x[s][1] = atom < lg.n_atoms ? src[1] : 0.f;
+      x[s][2] = atom < lg.n_atoms ? src[2] : 0.f;
+    }
+  } else {
+    q = r < lg.n_dof ? a.q[pose * a.q_stride + r] : 0.f;
+  }
+  const float dLdE = a.dLdE ? a.dLdE[pose] : 0.f;
+  const float E = eval_terms<LPP, APL, K, XIN>(L, q, x, g, rg, a.G[pi], pk.grid, w, gp, S, r, dLdE,
+                                               a.dLdE ? a.dLdG[pi] : nullptr, ek);
+  if (r == 0 && a.E) a.E[pose] = E;
+  if (!a.dLdE) return;
+  if (r == 0 && a.dLdw) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) atomicAdd(&a.dLdw[pi * K + k], dLdE * ek[k]);
+  }
+  if (a.dLdx) {
+#pragma unroll
+    for (int s = 0; s < APL; ++s) {
+      const int atom = APL * r + s;
+      if (atom < lg.n_atoms) {
+        float* d = a.dLdx + pose * a.xyz_stride + 3 * L.aorig[s];
+        d[0] += dLdE * g[s][0];
+        d[1] += dLdE * g[s][1];
+        d[2] += dLdE * g[s][2];
+      }
+    }
+  }
+  if (!XIN && a.dLdq) {
+    const float gq = chain_rule<LPP, APL>(L, rg, x, g, S, r);
+    if (r < lg.n_dof) a.dLdq[pose * a.q_stride + r] += dLdE * gq;
+  }
+}
+
+template <int K, bool XIN>
+static hipError_t launch_terms_k(const TermsArgs& a, int lpp, int apl, unsigned blocks, size_t lds,
+                                 hipStream_t s) {
+  if (lpp == 16 && apl == 1)
+    hipLaunchKernelGGL((terms_kernel<16, 1, K, XIN>), dim3(blocks), dim3(64), lds, s, a);
+  else if (lpp == 32 && apl == 1)
+    hipLaunchKernelGGL((terms_kernel<32, 1, K, XIN>), dim3(blocks), dim3(64), lds, s, a);
+  else if (lpp == 64 && apl == 1)
+    hipLaunchKernelGGL((terms_kernel<64, 1, K, XIN>), dim3(blocks), dim3(64), lds, s, a);
+  else
+    hipLaunchKernelGGL((terms_kernel<64, 2, K, XIN>), dim3(blocks), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_terms(const TermsArgs& a, int lpp, int apl, int K, hipStream_t s) {
+  const int gpb = 64 / lpp;
+  const unsigned blocks = unsigned((a.n_poses + gpb - 1) / gpb);
+  const size_t lds = score_lds_bytes(lpp, apl, a.max_pairs);
+  if (blocks == 0) return hipSuccess;
+  const bool xin = a.xyz != nullptr;
+  if (K == 3) return xin ? launch_terms_k<3, true>(a, lpp, apl, blocks, lds, s)
+                         : launch_terms_k<3, false>(a, lpp, apl, blocks, lds, s);
+  return xin ? launch_terms_k<5, true>(a, lpp, apl, blocks, lds, s)
+             : launch_terms_k<5, false>(a, lpp, apl, blocks, lds, s);
 }
 
 // ================================================================ sampler
@@ -228,10 +323,14 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const float*
     if (r == j) qn = L.lo + (L.hi - L.lo) * u01(w.y);
     float E;
     if (a.local_opt == DOCK_LOCAL_ADAM) {
+      // n_local gradient evaluations with an Adam update after each, then
+      // the energy of the refined pose: one evaluation site, n_local + 1 calls
       float m = 0.f, v = 0.f, b1t = 1.f, b2t = 1.f;
-      for (int t = 0; t < a.n_local; ++t) {
+      for (int t = 0;; ++t) {
         const EvalOut o = eval_pose<LPP, APL>(L, qn, M, grid, pairs, S, r);
         record(qn, o.g, o.E);
+        E = o.E;
+        if (t == a.n_local) break;
         m = a.b1 * m + (1.f - a.b1) * o.g;
         v = a.b2 * v + (1.f - a.b2) * o.g * o.g;
         b1t *= a.b1;
@@ -239,35 +338,42 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const float*
         const float mh = m / (1.f - b1t), vh = v / (1.f - b2t);
         if (dof) qn = wrap_clamp(qn - a.lr * mh / (sqrtf(vh) + a.eps), r, L);
       }
-      const EvalOut o = eval_pose<LPP, APL>(L, qn, M, grid, pairs, S, r);
-      record(qn, o.g, o.E);
-      E = o.E;
     } else {
-      EvalOut o = eval_pose<LPP, APL>(L, qn, M, grid, pairs, S, r);
-      record(qn, o.g, o.E);
-      E = o.E;
-      float g = o.g;
-      for (int l = 0; l < a.n_local; ++l) {
+      // Armijo line search as a loop over trial poses (one evaluation site):
+      // the first call scores the perturbed pose; each search tries
+      // alpha = 1, 1/2, ..., 2^-10 along -g/|g|; a failed search ends the
+      // refinement
+      float g = 0.f, d = 0.f, slope = 0.f, alpha = 1.f;
+      float qtry = qn;
+      int done_steps = 0, halvings = 0;
+      bool first = true;
+      E = 0.f;
+      for (;;) {
+        const EvalOut o = eval_pose<LPP, APL>(L, qtry, M, grid, pairs, S, r);
+        record(qtry, o.g, o.E);
+        if (first) {
+          E = o.E;
+          g = o.g;
+          first = false;
+        } else if (o.E <= E + 1e-4f * alpha * slope) {
+          qn = qtry;
+          E = o.E;
+          g = o.g;
+          ++done_steps;
+        } else {
+          if (++halvings > 10) break;
+          alpha *= 0.5f;
+          qtry = dof ? wrap_clamp(qn + alpha * d, r, L) : 0.f;
+          continue;
+        }
+        if (done_steps >= a.n_local) break;
         const float gn = sqrtf(group_sum<LPP>(dof ? g * g : 0.f));
         if (!(gn > 0.f)) break;
-        const float d = dof ? -g / gn : 0.f;
-        const float slope = -gn;
-        float alpha = 1.f;
-        bool ok = false;
-        for (int h = 0; h <= 10; ++h) {
-          const float qc = dof ? wrap_clamp(qn + alpha * d, r, L) : 0.f;
-          const EvalOut oc = eval_pose<LPP, APL>(L, qc, M, grid, pairs, S, r);
-          record(qc, oc.g, oc.E);
-          if (oc.E <= E + 1e-4f * alpha * slope) {
-            qn = qc;
-            E = oc.E;
-            g = oc.g;
-            ok = true;
-            break;
-          }
-          alpha *= 0.5f;
-        }
-        if (!ok) break;
+        d = dof ? -g / gn : 0.f;
+        slope = -gn;
+        alpha = 1.f;
+        halvings = 0;
+        qtry = dof ? wrap_clamp(qn + d, r, L) : 0.f;
       }
     }
     const float u = u01(w.z);
@@ -325,7 +431,7 @@ __global__ void __launch_bounds__(BLOCK) sample_kernel(SampleArgs a) {
     if (traj < a.n_traj) {
       const PocketDev pk = a.pockets[lg.pocket];
       LaneLig<APL> L;
-      load_lane_lig<LPP, APL>(L, lg, a.L.atoms, a.L.frags, a.L.tors, pk, r);
+      load_lane_lig<LPP, APL>(L, lg, a.L.ligs + lig, a.L.atoms, a.L.frags, a.L.tors, pk, r);
       run_traj<LPP, APL>(a, L, pk.M, pk.grid, sp, S, lig, traj, r);
     }
     __syncthreads();
@@ -380,7 +486,7 @@ __global__ void __launch_bounds__(64) best_kernel(BestArgs a) {
   none.preset = DOCK_PRESET_TRIDS;
   none.n_terms = 0;
   LaneLig<APL> L;
-  load_lane_lig<LPP, APL>(L, lg, a.L.atoms, a.L.frags, a.L.tors, none, r);
+  load_lane_lig<LPP, APL>(L, lg, a.L.ligs + lig, a.L.atoms, a.L.frags, a.L.tors, none, r);
   const int T = a.n_traj;
   for (int i = r; i < a.t_pad; i += 64) {
     float e = i < T ? a.E_best[size_t(lig) * T + i] : INFINITY;

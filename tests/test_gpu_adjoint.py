@@ -1,0 +1,243 @@
+"""GPU tests of the differentiable form (hand-written adjoint kernel behind a
+torch.autograd.Function) against the FP64 oracle.
+
+* tiny pocket, both presets, poses as DOFs and as coordinates: E, dL/dG at
+  every node, dL/dw, dL/dq, dL/dx against the oracle's analytic adjoint;
+* the differentiation workload (2,000-atom pocket, Vina-form terms, weights
+  ~ N(w0, 0.1|w0|), 64 ligands x 32 poses): per-pose E and dL/dq on sampled
+  poses against the oracle, dL/dx against FP64 central differences
+  (h = 1e-4), and at full size the exact identities
+  sum_nodes dL/dG[t][k] = w_k * sum_p dLdE_p * (#atoms of type t in pose p)
+  and dL/dw from the forward's linearity in w.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import topology, maps as MAPS, score as SC, adjoint as ADJ, fk as FK, params as P
+from tests import _gpu as G
+from tests._tiny import tiny_pocket, tiny_ligand
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return G.lib()
+
+
+def _poses(L, H, topos, n_per, rng):
+    qs = H.q_stride
+    Q, lig = [], []
+    for i, t in enumerate(topos):
+        q = np.zeros((n_per, qs), np.float32)
+        q[: n_per // 2, :t.n_dof] = G.poses_for(t, n_per // 2, rng, "near")
+        q[n_per // 2:, :t.n_dof] = G.poses_for(t, n_per - n_per // 2, rng, "uniform")
+        Q.append(q)
+        lig += [i] * n_per
+    return np.concatenate(Q), np.array(lig, np.int32)
+
+
+def _lazy_terms(pk, preset, grid, xs):
+    """Oracle per-term maps filled at the nodes the given coordinates touch."""
+    nx, ny, nz = pk.dims
+    Gd = np.zeros((8, P.n_terms(preset), nz, ny, nx))
+    c = np.concatenate([SC.cells(grid, x.reshape(-1, 3)) for x in xs])
+    idx = []
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                idx.append(((c[:, 2] + dz) * ny + c[:, 1] + dy) * nx + c[:, 0] + dx)
+    flat = np.unique(np.concatenate(idx))
+    vals = MAPS.build_maps(pk, preset, nodes=flat)
+    z, rem = np.divmod(flat, nx * ny)
+    y, x = np.divmod(rem, nx)
+    Gd[:, :, z, y, x] = vals
+    return Gd
+
+
+@pytest.mark.parametrize("preset", [P.PRESET_TRIDS, P.PRESET_VINA])
+@pytest.mark.parametrize("mode", ["q", "xyz"])
+def test_adjoint_tiny_against_oracle(D, preset, mode):
+    G.say("adjoint tiny preset", preset, "mode", mode)
+    pk = tiny_pocket(n=30, radius=7.0, grid=32)
+    grid = SC.grid_of(pk)
+    K = P.n_terms(preset)
+    rng = np.random.default_rng(10 + preset)
+    w = (np.asarray(P.default_weights(preset)) * (1 + 0.1 * rng.normal(size=K))).astype(np.float32)
+    p = G.load_pocket(pk, preset, w, keep=True)
+    L = synth.pack_ligands([synth.make_ligand(n, t, np.random.default_rng(n)) for n, t in
+                            ((5, 1), (9, 3), (14, 4))])
+    L.pocket_index = np.zeros(L.n_ligands, np.int32)
+    H = G.load_ligands(L)
+    topos = [topology.from_ligands(L, i) for i in range(L.n_ligands)]
+    Q, lig = _poses(L, H, topos, 8, rng)
+    dLdE = rng.normal(size=len(Q)).astype(np.float32)
+    Gref = MAPS.build_maps(pk, preset)
+    Ggpu = D.dock_pocket_maps(p, per_term=True)
+    wt = torch.tensor(w[None], device="cuda")
+    lt = torch.tensor(lig, device="cuda")
+    X = np.zeros((len(Q), H.max_atoms, 3), np.float32)
+    for i, t in enumerate(topos):
+        X[lig == i, :t.n_atoms] = FK.fk(t, Q[lig == i, :t.n_dof].astype(np.float64)).astype(np.float32)
+    kw = dict(q=torch.tensor(Q, device="cuda")) if mode == "q" else dict(xyz=torch.tensor(X, device="cuda"))
+    E = D.dock_score_terms(p, H, lt, wt, G=[Ggpu], **kw).cpu().numpy()
+    dLdG = torch.zeros_like(Ggpu)
+    dLdw = torch.zeros_like(wt)
+    dLdq = torch.zeros((len(Q), H.q_stride), device="cuda") if mode == "q" else None
+    dLdx = torch.zeros((len(Q), H.max_atoms, 3), device="cuda")
+    D.dock_score_adjoint(p, H, lt, wt, torch.tensor(dLdE, device="cuda"), G=[Ggpu], dLdG=[dLdG], dLdw=dLdw,
+                         dLdq=dLdq, dLdx=dLdx, **kw)
+    torch.cuda.synchronize()
+    dLdG = dLdG.cpu().numpy().astype(np.float64)
+    ref_G = np.zeros_like(Gref)
+    ref_w = np.zeros(K)
+    for i, t in enumerate(topos):
+        sel = lig == i
+        if mode == "q":
+            A = ADJ.adjoint(Gref, w, grid, preset, t, dLdE[sel], q=Q[sel, :t.n_dof].astype(np.float64))
+            Er = ADJ.energy(Gref, w, grid, preset, t, q=Q[sel, :t.n_dof].astype(np.float64))
+        else:
+            xs = X[sel, :t.n_atoms].astype(np.float64)
+            A = ADJ.adjoint(Gref, w, grid, preset, t, dLdE[sel], x=xs)
+            Er = ADJ.energy(Gref, w, grid, preset, t, x=xs)
+        ref_G += A["dLdG"]
+        ref_w += A["dLdw"]
+        sc = SC.Scorer(pk, preset, weights=w.astype(np.float64), G=Gref)
+        S_abs = sc.score(t, Q[sel, :t.n_dof].astype(np.float64))["S_abs"] if mode == "q" else np.abs(Er) + 1
+        assert np.all(np.abs(E[sel] - Er) <= 1e-5 * np.maximum(np.abs(Er), S_abs)), (E[sel], Er)
+        gx = dLdx.cpu().numpy()[sel, :t.n_atoms]
+        sx = np.linalg.norm(A["dLdx"].reshape(sel.sum(), -1), axis=1)
+        err = np.linalg.norm((gx - A["dLdx"]).reshape(sel.sum(), -1), axis=1)
+        assert np.all(err <= 1e-4 * sx + 1e-4), (err, sx)
+        if mode == "q":
+            gq = dLdq.cpu().numpy()[sel, :t.n_dof]
+            err = np.linalg.norm(gq - A["dLdq"], axis=1)
+            assert np.all(err <= 1e-4 * np.linalg.norm(A["dLdq"], axis=1) + 1e-4)
+    np.testing.assert_allclose(dLdw.cpu().numpy()[0], ref_w, rtol=1e-5, atol=1e-4 * np.abs(ref_w).max())
+    scale = np.abs(ref_G).max()
+    G.say("dLdG max |diff| / max |ref|", np.abs(dLdG - ref_G).max() / scale)
+    assert np.abs(dLdG - ref_G).max() <= 1e-5 * scale + 1e-7
+    # no contribution leaks outside the nodes the oracle touches
+    assert np.all(dLdG[np.abs(ref_G) == 0] == 0) or np.abs(dLdG[np.abs(ref_G) == 0]).max() < 1e-6 * scale
+
+
+def test_autograd_function_matches_direct_adjoint(D):
+    pk = tiny_pocket(n=30, radius=7.0, grid=32)
+    preset = P.PRESET_VINA
+    w = np.asarray(P.VINA_WEIGHTS, np.float32)
+    p = G.load_pocket(pk, preset, w, keep=True)
+    L = tiny_ligand(9, 3, seed=4)
+    L.pocket_index = np.zeros(1, np.int32)
+    H = G.load_ligands(L)
+    topo = topology.from_ligands(L, 0)
+    rng = np.random.default_rng(3)
+    Q = np.zeros((16, H.q_stride), np.float32)
+    Q[:, :topo.n_dof] = G.poses_for(topo, 16, rng, "near")
+    Gt = D.dock_pocket_maps(p, per_term=True).requires_grad_(True)
+    wt = torch.tensor(w[None], device="cuda", requires_grad=True)
+    qt = torch.tensor(Q, device="cuda", requires_grad=True)
+    lt = torch.zeros(16, dtype=torch.int32, device="cuda")
+    E = D.dock_score(p, H, lt, wt, Gt, q=qt)
+    c = torch.linspace(-1, 1, 16, device="cuda")
+    (E * c).sum().backward()
+    dG = torch.zeros_like(Gt)
+    dw = torch.zeros_like(wt)
+    dq = torch.zeros_like(qt)
+    D.dock_score_adjoint(p, H, lt, wt.detach(), c.contiguous(), q=qt.detach(), G=[Gt.detach()], dLdG=[dG],
+                         dLdw=dw, dLdq=dq)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(Gt.grad.cpu().numpy(), dG.cpu().numpy(), rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(wt.grad.cpu().numpy(), dw.cpu().numpy(), rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(qt.grad.cpu().numpy(), dq.cpu().numpy(), rtol=1e-5, atol=1e-5)
+
+
+def test_adjoint_differentiation_workload(D):
+    """2,000-atom pocket, Vina-form terms, weights ~ N(w0, 0.1|w0|), 64
+    ligands x 32 poses with q uniform in range (the differentiation workload)."""
+    pk, L, wl = synth.workload("C3")
+    pk = pk[0]
+    preset = P.PRESET_VINA
+    K = 5
+    w = synth.vina_weights(np.random.default_rng(33))
+    G.say("C3: weights", w)
+    p = G.load_pocket(pk, preset, w, keep=True)
+    H = G.load_ligands(L)
+    topos = [topology.from_ligands(L, i) for i in range(L.n_ligands)]
+    rng = np.random.default_rng(34)
+    T = wl["T"]
+    Q = np.zeros((L.n_ligands * T, H.q_stride), np.float32)
+    lig = np.repeat(np.arange(L.n_ligands), T).astype(np.int32)
+    for i, t in enumerate(topos):
+        Q[lig == i, :t.n_dof] = synth.random_poses(t.n_dof, t.box_min, t.box_max, T, rng)
+    c = rng.normal(size=len(Q)).astype(np.float32)
+    Gt = D.dock_pocket_maps(p, per_term=True).requires_grad_(True)
+    wt = torch.tensor(w[None], device="cuda", requires_grad=True)
+    qt = torch.tensor(Q, device="cuda", requires_grad=True)
+    lt = torch.tensor(lig, device="cuda")
+    ct = torch.tensor(c, device="cuda")
+    E = D.dock_score(p, H, lt, wt, Gt, q=qt)
+    (E * ct).sum().backward()
+    torch.cuda.synchronize()
+    En = E.detach().cpu().numpy()
+    dG = Gt.grad.cpu().numpy().astype(np.float64)
+    dw = wt.grad.cpu().numpy()[0].astype(np.float64)
+    dq = qt.grad.cpu().numpy()
+    # (1) node sums of dL/dG: corner weights of every atom sum to one
+    counts = np.zeros((len(Q), 8))
+    for i, t in enumerate(topos):
+        counts[lig == i] = np.bincount(t.types, minlength=8)
+    expect = np.einsum("p,pt->t", c.astype(np.float64), counts)[:, None] * w[None].astype(np.float64)
+    got = dG.reshape(8, K, -1).sum(-1)
+    G.say("node-sum identity max rel err", np.abs(got - expect).max() / np.abs(expect).max())
+    assert np.allclose(got, expect, rtol=1e-4, atol=1e-4 * np.abs(expect).max())
+    # (2) dL/dw from linearity of the forward in w (GPU forward, FP64 sum)
+    for k in range(K):
+        e = np.zeros((1, K), np.float32); e[0, k] = 1.0
+        Ep = D.dock_score_terms(p, H, lt, wt.detach() + torch.tensor(e, device="cuda"), q=qt.detach()).cpu().numpy()
+        Em = D.dock_score_terms(p, H, lt, wt.detach() - torch.tensor(e, device="cuda"), q=qt.detach()).cpu().numpy()
+        fd = float(np.dot(c.astype(np.float64), (Ep.astype(np.float64) - Em) / 2.0))
+        assert abs(fd - dw[k]) <= 2e-4 * (abs(dw[k]) + np.abs(c).sum()), (k, fd, dw[k])
+    # (3) sampled poses against the oracle (two per ligand): per-pose E and
+    #     dL/dq, and dL/dx against FP64 central differences with h = 1e-4
+    dx_gpu = torch.zeros((len(Q), H.max_atoms, 3), device="cuda")
+    D.dock_score_adjoint(p, H, lt, wt.detach(), ct, q=qt.detach(), G=[Gt.detach()], dLdx=dx_gpu)
+    dx_gpu = dx_gpu.cpu().numpy()
+    grid = SC.grid_of(pk)
+    picks = np.concatenate([np.flatnonzero(lig == i)[:2] for i in range(L.n_ligands)])
+    xs = [FK.fk(topos[lig[j]], Q[j:j + 1, :topos[lig[j]].n_dof].astype(np.float64)) for j in picks]
+    Gd = _lazy_terms(pk, preset, grid, xs)
+    w64 = w.astype(np.float64)
+    worst = [0.0, 0.0, 0.0]
+    n_fd = 0
+    for j in picks:
+        t = topos[lig[j]]
+        qj = Q[j:j + 1, :t.n_dof].astype(np.float64)
+        ref = SC.Scorer(pk, preset, weights=w64, G=Gd).score(t, qj)
+        A = ADJ.adjoint(Gd, w64, grid, preset, t, np.array([c[j]], np.float64), q=qj)
+        Er = ADJ.energy(Gd, w64, grid, preset, t, q=qj)[0]
+        if ref["margin_E"][0] > G.MARGIN:
+            worst[0] = max(worst[0], abs(En[j] - Er) / (1e-5 * max(abs(Er), ref["S_abs"][0])))
+        if ref["margin"][0] <= 2e-4:
+            continue
+        gq = dq[j, :t.n_dof]
+        worst[1] = max(worst[1], np.linalg.norm(gq - A["dLdq"][0]) / (1e-4 * np.linalg.norm(A["dLdq"][0]) + 1e-4))
+        if n_fd < 24:
+            n_fd += 1
+            x = ref["x"]
+            h = 1e-4
+            fd = np.zeros_like(x)
+            for a in range(t.n_atoms):
+                for cc in range(3):
+                    xp = x.copy(); xp[0, a, cc] += h
+                    xm = x.copy(); xm[0, a, cc] -= h
+                    fd[0, a, cc] = c[j] * (ADJ.energy(Gd, w64, grid, preset, t, x=xp)[0]
+                                           - ADJ.energy(Gd, w64, grid, preset, t, x=xm)[0]) / (2 * h)
+            gx = dx_gpu[j, :t.n_atoms]
+            worst[2] = max(worst[2], np.linalg.norm(gx - fd[0]) / (1e-4 * np.linalg.norm(fd[0]) + 1e-4))
+    G.say("C3 sampled: worst E/tol %.3g dLdq/tol %.3g dLdx-vs-FD/tol %.3g (%d FD poses)" % (*worst, n_fd))
+    assert worst[0] <= 1.0 and worst[1] <= 1.0 and worst[2] <= 1.0
+    assert n_fd >= 12

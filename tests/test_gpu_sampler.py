@@ -237,3 +237,21 @@ def test_best_energy_and_rmsd_distributions_over_seeds(D):
           % (pE, pR, np.median(Eg), np.median(Eo), lo, hi))
     assert pE >= 0.01 and pR >= 0.01
     assert lo <= 0.0 <= hi
+
+
+def test_autotuner_keeps_random_streams_and_runs(D, mixed):
+    p, H, L, _ = mixed
+    kw = dict(n_traj=16, n_local=3, seed=12)
+    D.dock_autotune_clear()
+    G.say("autotune")
+    base = _state(D, D.dock_sample(p, H, n_steps=0, **kw))
+    rep = D.dock_autotune(p, H, trial_steps=1, n_steps=2, **kw)
+    G.say("autotune report", rep)
+    assert len(rep) >= 3 and all(r["block"] in (64, 128, 256) for r in rep)
+    tuned = _state(D, D.dock_sample(p, H, n_steps=0, **kw))
+    # initial poses come from the (ligand, trajectory) Philox stream only
+    assert np.array_equal(base["q_cur"], tuned["q_cur"])
+    run = D.dock_sample(p, H, n_steps=3, **kw)
+    st = _state(D, run)
+    assert np.all(st["n_evals"] == 1 + 3 * 4) and np.all(np.isfinite(st["E_best"]))
+    D.dock_autotune_clear()
