@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=0, help="replay sampler launches as a hipGraph")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (every MI355X box here "
@@ -146,6 +148,16 @@ def main():
 
     def step(k):
         return one_step(D, pk, H, T, S, D.FORM_BATCHED, args.graph, seed=k)
+
+    if args.calib_copy_mib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the sampler kernel's counters in the same profiled run
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for k in range(args.warmup):
         step(1000 + k)

@@ -51,8 +51,18 @@ typedef enum {
 } dock_status;
 
 enum { DOCK_PRESET_TRIDS = 0, DOCK_PRESET_VINA = 1 };
-enum { DOCK_LOCAL_ADAM = 0, DOCK_LOCAL_LINESEARCH = 1 };
+/* Local refinement rules: Adam (the paper's choice, Methods), an Armijo line
+ * search, and the alternatives the paper compares in Table S5. */
+enum {
+  DOCK_LOCAL_ADAM = 0,
+  DOCK_LOCAL_LINESEARCH = 1,
+  DOCK_LOCAL_SGD = 2,
+  DOCK_LOCAL_RMSPROP = 3,
+  DOCK_LOCAL_ADAGRAD = 4,
+  DOCK_LOCAL_ADAMW = 5
+};
 enum { DOCK_FORM_PLAIN = 0, DOCK_FORM_BATCHED = 1 };
+enum { DOCK_INTER_GRID = 0, DOCK_INTER_DIRECT = 1 };
 
 typedef struct dock_pocket_s* dock_pocket_t;
 typedef struct dock_ligands_s* dock_ligands_t;
@@ -81,6 +91,13 @@ typedef struct {
   const float* weights;   /* host [K] or NULL for the preset's weights
                              (TRIDS 0.2 / 10 / 0.6, Methods E_dock) */
   int32_t keep_per_term;  /* nonzero: also keep G (needed by the adjoint) */
+  int32_t inter_mode;     /* DOCK_INTER_GRID: receptor terms from the grid maps
+                             (+ 10 |x - clamp(x)|_1 outside the map box);
+                             DOCK_INTER_DIRECT: summed pair by pair over the
+                             receptor atoms inside the cutoffs, found through a
+                             cell list of half-cutoff cells (the paper's cutoff
+                             pair kernel, Discussion item 4); no maps, no box
+                             term, not usable by the differentiable form */
 } dock_pocket_desc;
 
 /* Builds the maps on `stream`; the returned handle owns them.  The call
@@ -200,7 +217,9 @@ typedef struct {
   int32_t n_traj;           /* trajectories per ligand, >= 1 */
   int32_t n_steps;          /* MC steps, >= 0 */
   int32_t n_local;          /* local steps per MC step, >= 0 */
-  int32_t local_opt;        /* DOCK_LOCAL_ADAM or DOCK_LOCAL_LINESEARCH */
+  int32_t local_opt;        /* DOCK_LOCAL_*: Adam (lr, beta1, beta2, eps), line search,
+                               SGD (lr), RMSprop (lr, rms_alpha, eps), AdaGrad (lr, eps),
+                               AdamW (Adam + weight_decay); state resets every MC step */
   float lr, beta1, beta2, eps;
   float mc_beta;            /* 0.069 */
   uint32_t seed;
@@ -210,6 +229,8 @@ typedef struct {
   int32_t steps_per_launch; /* 0: all steps in one launch per bucket */
   int32_t record_trace;     /* store q, E, dE/dq of every evaluation (tests) */
   int32_t lanes_per_pose;   /* 0: planner choice; else 16, 32 or 64 */
+  float rms_alpha;          /* RMSprop smoothing (0.99) */
+  float weight_decay;       /* AdamW decoupled weight decay (0.01) */
 } dock_sample_params;
 
 void dock_sample_params_default(dock_sample_params* p);

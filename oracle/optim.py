@@ -12,6 +12,15 @@ direction d = -g/|g|, alpha = 2^-j for j = 0..10, the first alpha with
 is taken; if none is, the pose stays and its refinement ends.  After every
 update the angles are wrapped to [-pi, pi) and the translation is clamped to
 the box.
+
+Optimiser variants compared in Table S5 (AdamW, RMSprop, AdaGrad, SGD), each
+with the same learning rate, moments reset per MC step, and the PyTorch
+default hyper-parameters as reading (RMSprop alpha 0.99, AdamW weight decay
+0.01, eps as Adam's):
+  SGD      q <- q - lr g
+  RMSprop  v <- a v + (1-a) g^2;  q <- q - lr g / (sqrt(v) + eps)
+  AdaGrad  s <- s + g^2;          q <- q - lr g / (sqrt(s) + eps)
+  AdamW    q <- q (1 - lr wd), then the Adam step
 """
 import numpy as np
 
@@ -19,6 +28,10 @@ from . import params as P
 
 ARMIJO_C = 1e-4
 LS_MAX_HALVINGS = 10
+
+ADAM, LINESEARCH, SGD, RMSPROP, ADAGRAD, ADAMW = range(6)
+RMS_ALPHA = 0.99
+WEIGHT_DECAY = 0.01
 
 
 def wrap_clamp(q, box_min, box_max):
@@ -50,6 +63,36 @@ def adam_refine(score_fn, q, n_local, box_min, box_max, lr=P.ADAM_LR, b1=P.ADAM_
     E, g = score_fn(q)
     if trace is not None:
         trace.append((q.copy(), E.copy(), g.copy()))
+    return q, E
+
+
+def first_order_refine(kind, score_fn, q, n_local, box_min, box_max, lr=P.ADAM_LR, b1=P.ADAM_B1,
+                       b2=P.ADAM_B2, eps=P.ADAM_EPS, alpha=RMS_ALPHA, wd=WEIGHT_DECAY):
+    """n_local steps of SGD / RMSprop / AdaGrad / AdamW; returns (q, E)."""
+    if kind == ADAM:
+        return adam_refine(score_fn, q, n_local, box_min, box_max, lr, b1, b2, eps)
+    q = np.array(q, np.float64, copy=True)
+    m = np.zeros_like(q)
+    v = np.zeros_like(q)
+    for t in range(1, n_local + 1):
+        E, g = score_fn(q)
+        if kind == SGD:
+            step = lr * g
+        elif kind == RMSPROP:
+            v = alpha * v + (1 - alpha) * g * g
+            step = lr * g / (np.sqrt(v) + eps)
+        elif kind == ADAGRAD:
+            v = v + g * g
+            step = lr * g / (np.sqrt(v) + eps)
+        elif kind == ADAMW:
+            q = q * (1 - lr * wd)
+            m = b1 * m + (1 - b1) * g
+            v = b2 * v + (1 - b2) * g * g
+            step = lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+        else:
+            raise ValueError(kind)
+        q = wrap_clamp(q - step, box_min, box_max)
+    E, g = score_fn(q)
     return q, E
 
 

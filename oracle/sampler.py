@@ -24,8 +24,12 @@ from . import philox as PX
 from . import optim
 
 
-LOCAL_ADAM = 0
-LOCAL_LINESEARCH = 1
+LOCAL_ADAM = optim.ADAM
+LOCAL_LINESEARCH = optim.LINESEARCH
+LOCAL_SGD = optim.SGD
+LOCAL_RMSPROP = optim.RMSPROP
+LOCAL_ADAGRAD = optim.ADAGRAD
+LOCAL_ADAMW = optim.ADAMW
 
 
 @dataclass
@@ -103,9 +107,12 @@ def run_steps(scorer, topo, lig_id, prm, state, n_steps, traj=None, trace=None,
         if prm.local_opt == LOCAL_ADAM:
             q, E = optim.adam_refine(score_fn, q, prm.n_local, topo.box_min, topo.box_max,
                                      prm.lr, prm.beta1, prm.beta2, prm.eps)
-        else:
+        elif prm.local_opt == LOCAL_LINESEARCH:
             q, E = optim.linesearch_refine(score_fn, q, prm.n_local, topo.box_min,
                                            topo.box_max, n_evals=n_evals)
+        else:
+            q, E = optim.first_order_refine(prm.local_opt, score_fn, q, prm.n_local, topo.box_min,
+                                            topo.box_max, prm.lr, prm.beta1, prm.beta2, prm.eps)
         u = PX.to_unit(w[2])
         dE = E - state.E_cur
         with np.errstate(over="ignore"):

@@ -272,9 +272,12 @@ class DirectScorer:
         self.weights = np.asarray(P.default_weights(preset) if weights is None else weights,
                                   np.float64)
 
-    def inter_atoms(self, types, x):
+    def inter_atoms(self, types, x, extras=False):
         Pn, N, _ = x.shape
         e = np.zeros((Pn, N)); g = np.zeros((Pn, N, 3))
+        eabs = np.zeros((Pn, N))
+        margin = np.full(Pn, np.inf)
+        margin_e = np.full(Pn, np.inf)
         for a in range(N):
             t = int(types[a])
             r = x[:, a, None, :] - self.rec[None]          # [P, R, 3]
@@ -286,15 +289,32 @@ class DirectScorer:
                 dd = d[:, sel]
                 within = terms.within_fp64(self.preset, dd, t, tr)
                 vals, dvals = terms.pair_energy_terms(self.preset, dd, t, tr, within)
-                e[:, a] += np.einsum("k,kpr->p", self.weights, vals)
+                ep = np.einsum("k,kpr->pr", self.weights, vals)
+                e[:, a] += ep.sum(1)
+                eabs[:, a] += np.abs(ep).sum(1)
                 de = np.einsum("k,kpr->pr", self.weights, dvals)
                 g[:, a] += np.einsum("pr,prc->pc", de / dd, r[:, sel])
+                if extras:
+                    for b in _breakpoints(self.preset, t, tr):
+                        margin = np.minimum(margin, np.abs(dd - b).min(1))
+                    for b in _jumps(self.preset, t, tr):
+                        margin_e = np.minimum(margin_e, np.abs(dd - b).min(1))
+        if extras:
+            return e, g, eabs, margin, margin_e
         return e, g
 
-    def score(self, topo, q):
+    def score(self, topo, q, want_parts=False):
         q = np.atleast_2d(np.asarray(q, np.float64))
         x = FK.fk(topo, q)
-        e, g = self.inter_atoms(topo.types, x)
-        Ei, gi, _, _, _ = intra(topo, self.preset, self.weights, x)
+        e, g, eabs, m1, m1e = self.inter_atoms(topo.types, x, extras=True)
+        Ei, gi, sabs_i, mi, mie = intra(topo, self.preset, self.weights, x)
         gat = g + gi
-        return dict(E=e.sum(1) + Ei, dEdq=FK.dof_gradient(topo, q, x, gat), x=x, g=gat)
+        out = dict(E=e.sum(1) + Ei, dEdq=FK.dof_gradient(topo, q, x, gat), x=x, g=gat,
+                   S_abs=eabs.sum(1) + sabs_i, margin=np.minimum(m1, mi),
+                   margin_E=np.minimum(m1e, mie))
+        if want_parts:
+            out.update(E_inter=e.sum(1), E_intra=Ei)
+        return out
+
+    def energy(self, topo, q):
+        return self.score(topo, q)["E"]

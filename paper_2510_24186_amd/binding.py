@@ -20,8 +20,9 @@ lib = C.CDLL(LIB_PATH)
 
 DOCK_OK = 0
 PRESET_TRIDS, PRESET_VINA = 0, 1
-LOCAL_ADAM, LOCAL_LINESEARCH = 0, 1
+LOCAL_ADAM, LOCAL_LINESEARCH, LOCAL_SGD, LOCAL_RMSPROP, LOCAL_ADAGRAD, LOCAL_ADAMW = range(6)
 FORM_PLAIN, FORM_BATCHED = 0, 1
+INTER_GRID, INTER_DIRECT = 0, 1
 ERRORS = {-1: "DOCK_E_ARG", -2: "DOCK_E_TOPOLOGY", -3: "DOCK_E_LIMIT", -4: "DOCK_E_OOM", -5: "DOCK_E_HIP"}
 
 _p = C.c_void_p
@@ -32,7 +33,7 @@ _f32 = C.c_float
 class PocketDesc(C.Structure):
     _fields_ = [("n_atoms", _i32), ("xyz", _p), ("type", _p), ("origin", _f32 * 3),
                 ("spacing", _f32), ("dims", _i32 * 3), ("preset", _i32), ("weights", _p),
-                ("keep_per_term", _i32)]
+                ("keep_per_term", _i32), ("inter_mode", _i32)]
 
 
 class LigandDesc(C.Structure):
@@ -51,7 +52,8 @@ class SampleParams(C.Structure):
     _fields_ = [("n_traj", _i32), ("n_steps", _i32), ("n_local", _i32), ("local_opt", _i32),
                 ("lr", _f32), ("beta1", _f32), ("beta2", _f32), ("eps", _f32), ("mc_beta", _f32),
                 ("seed", C.c_uint32), ("form", _i32), ("use_graph", _i32),
-                ("steps_per_launch", _i32), ("record_trace", _i32), ("lanes_per_pose", _i32)]
+                ("steps_per_launch", _i32), ("record_trace", _i32), ("lanes_per_pose", _i32),
+                ("rms_alpha", _f32), ("weight_decay", _f32)]
 
 
 class RunView(C.Structure):
@@ -171,7 +173,7 @@ class Pocket:
 
 
 def dock_load_pocket(xyz, types, origin, spacing, dims, preset=PRESET_TRIDS, weights=None,
-                     keep_per_term=False, stream=None):
+                     keep_per_term=False, inter_mode=INTER_GRID, stream=None):
     xyz = _np(xyz, np.float32).reshape(-1, 3)
     types = _np(types, np.uint8)
     d = PocketDesc()
@@ -185,6 +187,7 @@ def dock_load_pocket(xyz, types, origin, spacing, dims, preset=PRESET_TRIDS, wei
     w = None if weights is None else _np(weights, np.float32)
     d.weights = _ptr(w)
     d.keep_per_term = int(bool(keep_per_term))
+    d.inter_mode = int(inter_mode)
     h = _p()
     _check(lib.dock_load_pocket(C.byref(d), _stream(stream), C.byref(h)))
     pr = _i32()

@@ -58,6 +58,9 @@ struct dock_pocket_s {
   float4* d_rec = nullptr;
   float* d_M = nullptr;
   float* d_G = nullptr;
+  float4* d_sorted = nullptr;   // direct mode
+  int* d_cells = nullptr;
+  float2* d_tp = nullptr;
 };
 
 struct dock_ligands_s {
@@ -167,6 +170,10 @@ int dock_load_pocket(const dock_pocket_desc* d, void* stream, dock_pocket_t* out
     return fail(DOCK_E_ARG, "bad receptor arrays");
   if (d->preset != DOCK_PRESET_TRIDS && d->preset != DOCK_PRESET_VINA)
     return fail(DOCK_E_ARG, "unknown preset");
+  if (d->inter_mode != DOCK_INTER_GRID && d->inter_mode != DOCK_INTER_DIRECT)
+    return fail(DOCK_E_ARG, "unknown inter_mode");
+  if (d->inter_mode == DOCK_INTER_DIRECT && d->keep_per_term)
+    return fail(DOCK_E_ARG, "per-term maps need inter_mode DOCK_INTER_GRID");
   if (!(d->spacing > 0.f) || !std::isfinite(d->spacing)) return fail(DOCK_E_ARG, "bad spacing");
   for (int c = 0; c < 3; ++c) {
     if (d->dims[c] < 2 || d->dims[c] > 1024) return fail(DOCK_E_ARG, "grid dims must be in [2, 1024]");
@@ -213,9 +220,66 @@ int dock_load_pocket(const dock_pocket_desc* d, void* stream, dock_pocket_t* out
     dev_free(p->d_rec);
     dev_free(p->d_M);
     dev_free(p->d_G);
+    dev_free(p->d_sorted);
+    dev_free(p->d_cells);
+    dev_free(p->d_tp);
     delete p;
     return fail(code, m);
   };
+  pd.inter_mode = d->inter_mode;
+  if (d->inter_mode == DOCK_INTER_DIRECT) {
+    // cell list: cells of half the largest cutoff over the receptor's bounds
+    const double cell = (d->preset == DOCK_PRESET_TRIDS ? 10.0 : 8.0) / 2.0;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = hi[c] = d->n_atoms ? d->xyz[c] : 0.0;
+      for (int i = 1; i < d->n_atoms; ++i) {
+        lo[c] = std::min(lo[c], double(d->xyz[3 * i + c]));
+        hi[c] = std::max(hi[c], double(d->xyz[3 * i + c]));
+      }
+      pd.cell_origin[c] = float(lo[c]);
+      pd.cell_dims[c] = std::max(1, int(std::floor((hi[c] - double(pd.cell_origin[c])) / cell)) + 1);
+    }
+    pd.inv_cell = float(1.0 / cell);
+    const size_t ncell = size_t(pd.cell_dims[0]) * pd.cell_dims[1] * pd.cell_dims[2];
+    if (ncell > (size_t(1) << 26)) return cleanup(DOCK_E_LIMIT, "receptor too extended for the cell list");
+    std::vector<int> cidx(d->n_atoms), start(ncell + 1, 0);
+    for (int i = 0; i < d->n_atoms; ++i) {
+      int ic[3];
+      for (int c = 0; c < 3; ++c) {
+        const float u = (d->xyz[3 * i + c] - pd.cell_origin[c]) * pd.inv_cell;
+        ic[c] = std::min(std::max(int(std::floor(u)), 0), pd.cell_dims[c] - 1);
+      }
+      cidx[i] = (ic[2] * pd.cell_dims[1] + ic[1]) * pd.cell_dims[0] + ic[0];
+      start[cidx[i] + 1]++;
+    }
+    for (size_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+    std::vector<float4> sorted(std::max(1, d->n_atoms));
+    std::vector<int> fill(start.begin(), start.end() - 1);
+    for (int i = 0; i < d->n_atoms; ++i) sorted[fill[cidx[i]]++] = rec[i];
+    TypePair tab[kTypes * kTypes];
+    type_pair_table(d->preset, tab);
+    std::vector<float2> tp(kTypes * kTypes);
+    for (int k = 0; k < kTypes * kTypes; ++k) {
+      tp[k].x = tab[k].rsum;
+      std::memcpy(&tp[k].y, &tab[k].flags, 4);
+    }
+    hipError_t e = dev_alloc(&p->d_sorted, sorted.size());
+    if (e == hipSuccess) e = dev_alloc(&p->d_cells, start.size());
+    if (e == hipSuccess) e = dev_alloc(&p->d_tp, tp.size());
+    if (e != hipSuccess) return cleanup(DOCK_E_OOM, std::string("cell list allocation: ") + hipGetErrorString(e));
+    e = hipMemcpy(p->d_sorted, sorted.data(), sizeof(float4) * sorted.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_cells, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_tp, tp.data(), sizeof(float2) * tp.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(DOCK_E_HIP, std::string("cell list upload: ") + hipGetErrorString(e));
+    pd.rec = p->d_sorted;
+    pd.cell_start = p->d_cells;
+    pd.tp = p->d_tp;
+    pd.M = nullptr;
+    pd.G = nullptr;
+    *out = p;
+    return DOCK_OK;
+  }
   hipError_t e = dev_alloc(&p->d_rec, rec.size());
   if (e == hipSuccess) e = dev_alloc(&p->d_M, size_t(kTypes) * nodes);
   if (e == hipSuccess && d->keep_per_term) e = dev_alloc(&p->d_G, size_t(kTypes) * K * nodes);
@@ -242,6 +306,7 @@ int dock_load_pocket(const dock_pocket_desc* d, void* stream, dock_pocket_t* out
 
 int dock_pocket_maps(dock_pocket_t p, int32_t per_term, float** dev_ptr, int64_t* n_floats) {
   if (!p || !dev_ptr) return fail(DOCK_E_ARG, "null argument");
+  if (p->dev.inter_mode == DOCK_INTER_DIRECT) return fail(DOCK_E_ARG, "a direct-mode pocket has no maps");
   const long long nodes = (long long)p->dev.grid.dims[0] * p->dev.grid.dims[1] * p->dev.grid.dims[2];
   if (per_term) {
     if (!p->d_G) return fail(DOCK_E_ARG, "per-term maps were not kept");
@@ -281,6 +346,9 @@ int dock_free_pocket(dock_pocket_t p) {
   dev_free(p->d_rec);
   dev_free(p->d_M);
   dev_free(p->d_G);
+  dev_free(p->d_sorted);
+  dev_free(p->d_cells);
+  dev_free(p->d_tp);
   delete p;
   return DOCK_OK;
 }
@@ -544,6 +612,9 @@ static int check_pockets(const dock_pocket_t* pockets, int n_pockets, dock_ligan
   if (!pockets || n_pockets < 1) return fail(DOCK_E_ARG, "no pockets");
   for (int i = 0; i < n_pockets; ++i)
     if (!pockets[i]) return fail(DOCK_E_ARG, "null pocket handle");
+  for (int i = 1; i < n_pockets; ++i)
+    if (pockets[i]->dev.inter_mode != pockets[0]->dev.inter_mode)
+      return fail(DOCK_E_ARG, "pockets of one call must share inter_mode");
   for (int i = 0; i < L->n; ++i)
     if (L->host[i].pocket >= n_pockets) return fail(DOCK_E_ARG, "ligand pocket index out of range");
   if (L->host_only) return fail(DOCK_E_ARG, "ligand handle was loaded host_only");
@@ -588,7 +659,8 @@ int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligand
   a.xyz = xyz_out;
   a.xyz_stride = xyz_stride;
   a.max_pairs = L->max_pairs;
-  HIP_TRY(launch_score(a, lpp, apl, reinterpret_cast<hipStream_t>(stream)));
+  HIP_TRY(launch_score(a, lpp, apl, pockets[0]->dev.inter_mode == DOCK_INTER_DIRECT,
+                       reinterpret_cast<hipStream_t>(stream)));
   return DOCK_OK;
 }
 
@@ -619,6 +691,8 @@ static int terms_call(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   if (rc) return rc;
   TermsArgs a{};
   for (int i = 0; i < n_pockets; ++i) {
+    if (pockets[i]->dev.inter_mode != DOCK_INTER_GRID)
+      return fail(DOCK_E_ARG, "the differentiable form needs grid-mode pockets");
     const float* gi = (G && G[i]) ? G[i] : pockets[i]->d_G;
     if (!gi) return fail(DOCK_E_ARG, "no per-term maps for pocket " + std::to_string(i));
     a.G[i] = gi;
@@ -691,6 +765,8 @@ void dock_sample_params_default(dock_sample_params* p) {
   p->steps_per_launch = 0;
   p->record_trace = 0;
   p->lanes_per_pose = 0;
+  p->rms_alpha = 0.99f;
+  p->weight_decay = 0.01f;
 }
 
 struct Bucket {
@@ -704,6 +780,7 @@ struct dock_run_s {
   dock_ligands_t L = nullptr;
   std::vector<dock_pocket_t> pockets;
   const PocketDev* table = nullptr;
+  bool direct = false;
   dock_sample_params p{};
   int n_lig = 0, T = 0, q_stride = 0, step = 0, trace_cap = 0;
   float *q_cur = nullptr, *E_cur = nullptr, *q_best = nullptr, *E_best = nullptr, *trace = nullptr;
@@ -750,7 +827,7 @@ static hipError_t timed_launch(dock_run_s* r, const SampleArgs& a, int bucket, i
     eb = pool_event(r);
     if (ea) (void)hipEventRecord(ea, s);
   }
-  hipError_t e = launch_sample(a, lpp, apl, grid, block, s);
+  hipError_t e = launch_sample(a, lpp, apl, grid, block, r->direct, s);
   if (r->recording && ea && eb) {
     (void)hipEventRecord(eb, s);
     dock_run_s::Launch L;
@@ -802,6 +879,8 @@ static SampleArgs base_args(const dock_run_s* r) {
   a.b2 = r->p.beta2;
   a.eps = r->p.eps;
   a.mc_beta = r->p.mc_beta;
+  a.rms_alpha = r->p.rms_alpha;
+  a.weight_decay = r->p.weight_decay;
   a.seed = r->p.seed;
   a.q_cur = r->q_cur;
   a.E_cur = r->E_cur;
@@ -907,13 +986,14 @@ static int timed_phases(dock_run_s* r, bool init, int steps, hipStream_t s) {
 static int check_params(const dock_sample_params* p) {
   if (!p) return fail(DOCK_E_ARG, "null params");
   if (p->n_traj < 1 || p->n_steps < 0 || p->n_local < 0) return fail(DOCK_E_ARG, "bad counts");
-  if (p->local_opt != DOCK_LOCAL_ADAM && p->local_opt != DOCK_LOCAL_LINESEARCH)
+  if (p->local_opt < DOCK_LOCAL_ADAM || p->local_opt > DOCK_LOCAL_ADAMW)
     return fail(DOCK_E_ARG, "unknown local_opt");
   if (p->form != DOCK_FORM_PLAIN && p->form != DOCK_FORM_BATCHED) return fail(DOCK_E_ARG, "unknown form");
   if (p->lanes_per_pose != 0 && p->lanes_per_pose != 16 && p->lanes_per_pose != 32 && p->lanes_per_pose != 64)
     return fail(DOCK_E_ARG, "lanes_per_pose must be 0, 16, 32 or 64");
   if (!(std::isfinite(p->lr) && std::isfinite(p->beta1) && std::isfinite(p->beta2) &&
-        std::isfinite(p->eps) && std::isfinite(p->mc_beta)))
+        std::isfinite(p->eps) && std::isfinite(p->mc_beta) && std::isfinite(p->rms_alpha) &&
+        std::isfinite(p->weight_decay)))
     return fail(DOCK_E_ARG, "non-finite sampler constant");
   if (p->steps_per_launch < 0) return fail(DOCK_E_ARG, "negative steps_per_launch");
   return DOCK_OK;
@@ -938,6 +1018,7 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   if (!r) return fail(DOCK_E_OOM, "host allocation");
   r->L = L;
   r->pockets.assign(pockets, pockets + n_pockets);
+  r->direct = pockets[0]->dev.inter_mode == DOCK_INTER_DIRECT;
   r->p = *p;
   r->n_lig = L->n;
   r->T = p->n_traj;
@@ -1020,7 +1101,7 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
       B.n_items = int(items.size()) - B.item_off;
       const size_t lds = sample_lds_bytes(B.lpp, B.apl, B.block, B.max_pairs);
       if (lds > 64 * 1024) return bail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
-      const int per_cu = sample_max_blocks_per_cu(B.lpp, B.apl, B.block, lds);
+      const int per_cu = sample_max_blocks_per_cu(B.lpp, B.apl, B.block, r->direct, lds);
       B.grid = std::min(B.n_items, per_cu * n_cu);
     }
   }
@@ -1040,7 +1121,7 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   if (e == hipSuccess) e = dev_alloc(&r->d_items, items.size());
   if (e == hipSuccess) e = dev_alloc(&r->d_queue, size_t(std::max(1, r->n_queue)));
   if (e == hipSuccess && p->record_trace) {
-    const int per_step = p->local_opt == DOCK_LOCAL_ADAM ? p->n_local + 1 : 1 + 11 * p->n_local;
+    const int per_step = p->local_opt == DOCK_LOCAL_LINESEARCH ? 1 + 11 * p->n_local : p->n_local + 1;
     r->trace_cap = 1 + p->n_steps * per_step;
     e = dev_alloc(&r->trace, nt * size_t(r->trace_cap) * (2 * r->q_stride + 1));
   }

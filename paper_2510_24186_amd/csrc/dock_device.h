@@ -331,6 +331,54 @@ DK_INLINE Trilerp trilerp(const float* __restrict__ M, const GridDev& g, float p
   return t;
 }
 
+// ------------------------------------------------------------------ direct pair mode
+// Receptor terms summed pair by pair over the atoms inside the cutoff (the
+// paper's cutoff pair kernel).  Cells are half a cutoff wide, so every
+// receptor atom within the cutoff lies in the 5 x 5 x 5 cells around the
+// ligand atom's cell; for fixed (z, y) the run of 5 x-cells is one contiguous
+// range of the cell-sorted atom array.
+DK_INLINE void inter_direct(const PocketDev& pk, int preset, const float* w, int lt, float px, float py,
+                            float pz, float& e, float& gx, float& gy, float& gz) {
+  e = gx = gy = gz = 0.f;
+  const float cut2 = preset == DOCK_PRESET_TRIDS ? 100.0f : 64.0f;
+  int lo[3], hi[3];
+  const float p[3] = {px, py, pz};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float u = fminf(fmaxf((p[c] - pk.cell_origin[c]) * pk.inv_cell, -8.0f), float(pk.cell_dims[c] + 8));
+    const int ic = int(floorf(u));
+    lo[c] = max(ic - 2, 0);
+    hi[c] = min(ic + 2, pk.cell_dims[c] - 1);
+  }
+  if (lo[0] > hi[0]) return;
+  const int nx = pk.cell_dims[0], nxy = pk.cell_dims[0] * pk.cell_dims[1];
+  for (int z = lo[2]; z <= hi[2]; ++z) {
+    for (int y = lo[1]; y <= hi[1]; ++y) {
+      const int row = z * nxy + y * nx;
+      const int b = pk.cell_start[row + lo[0]], end = pk.cell_start[row + hi[0] + 1];
+      for (int i = b; i < end; ++i) {
+        const float4 rr = pk.rec[i];
+        const float dx = px - rr.x, dy = py - rr.y, dz = pz - rr.z;
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        if (!(d2 < cut2)) continue;
+        const float2 tp = pk.tp[lt * kTypes + (__float_as_int(rr.w) & 0xff)];
+        const float inv_d = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
+        const float d = d2 * inv_d;
+        float ee, de;
+        if (preset == DOCK_PRESET_TRIDS)
+          trids_pair(d2, d, tp.x, __float_as_uint(tp.y), w, ee, de);
+        else
+          vina_pair(d2, d, tp.x, __float_as_uint(tp.y), w, ee, de);
+        e += ee;
+        const float cf = de * inv_d;
+        gx += cf * dx;
+        gy += cf * dy;
+        gz += cf * dz;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ pose evaluation
 // Static per-ligand data held in registers by each lane of a group.
 template <int APL>
@@ -597,11 +645,10 @@ DK_INLINE float chain_rule(const LaneLig<APL>& L, const Rigid& rg, const float (
 
 // One evaluation of E and dE/dq at the pose whose DOF r is held by lane r.
 // Optionally leaves world coordinates and atom gradients in xo/go.
-template <int LPP, int APL, bool WANT_X = false>
-DK_INLINE EvalOut eval_pose(const LaneLig<APL>& L, float q, const float* __restrict__ M,
-                            const GridDev& grid, const PairRec* __restrict__ pairs,
-                            const GroupSlab& S, int r, float (*xo)[3] = nullptr,
-                            float (*go)[3] = nullptr) {
+template <int LPP, int APL, bool WANT_X = false, bool DIRECT = false>
+DK_INLINE EvalOut eval_pose(const LaneLig<APL>& L, float q, const PocketDev& pk,
+                            const PairRec* __restrict__ pairs, const GroupSlab& S, int r,
+                            float (*xo)[3] = nullptr, float (*go)[3] = nullptr) {
   // ---- atoms: place, interpolate, publish coordinates to the slab
   float x[APL][3], g[APL][3];
   const Rigid rg = fk_place<LPP, APL>(L, q, r, x);
@@ -610,12 +657,19 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& L, float q, const float* __restr
   for (int s = 0; s < APL; ++s) {
     const int atom = APL * r + s;
     if (atom < L.n_atoms) {
-      const size_t nxyz = size_t(grid.dims[0]) * grid.dims[1] * grid.dims[2];
-      const Trilerp tl = trilerp(M + size_t(L.atype[s]) * nxyz, grid, x[s][0], x[s][1], x[s][2]);
-      e_lane += tl.v + tl.eout;
-      g[s][0] = tl.gx;
-      g[s][1] = tl.gy;
-      g[s][2] = tl.gz;
+      if (DIRECT) {
+        float ei;
+        inter_direct(pk, L.preset, L.w, L.atype[s], x[s][0], x[s][1], x[s][2], ei, g[s][0], g[s][1],
+                     g[s][2]);
+        e_lane += ei;
+      } else {
+        const size_t nxyz = size_t(pk.grid.dims[0]) * pk.grid.dims[1] * pk.grid.dims[2];
+        const Trilerp tl = trilerp(pk.M + size_t(L.atype[s]) * nxyz, pk.grid, x[s][0], x[s][1], x[s][2]);
+        e_lane += tl.v + tl.eout;
+        g[s][0] = tl.gx;
+        g[s][1] = tl.gy;
+        g[s][2] = tl.gz;
+      }
       S.xs[atom] = make_float4(x[s][0], x[s][1], x[s][2], 0.f);
       S.fx[atom] = 0.f;
       S.fy[atom] = 0.f;

@@ -71,6 +71,16 @@ struct PocketDev {
   const float* G;   // per-term maps [8][K][nz][ny][nx] (may be null)
   int preset, n_terms;
   float w[kMaxTerms];
+  // direct pair mode: receptor atoms sorted by cell (w = type bits), cell
+  // offsets [ncells + 1], per (ligand type, receptor type) radius sum and
+  // flags (x = rsum, y = flags bits)
+  int inter_mode;
+  const float4* rec;
+  const int* cell_start;
+  const float2* tp;
+  float cell_origin[3];
+  float inv_cell;
+  int cell_dims[3];
 };
 
 // ---------------------------------------------------------------- host side

@@ -65,7 +65,7 @@ struct SampleArgs {
   int init;               // draw initial poses and score them instead of stepping
   int n_traj, q_stride;
   int n_local, local_opt;
-  float lr, b1, b2, eps, mc_beta;
+  float lr, b1, b2, eps, mc_beta, rms_alpha, weight_decay;
   unsigned seed;
   float* q_cur;
   float* E_cur;
@@ -110,14 +110,15 @@ size_t sample_lds_bytes(int lpp, int apl, int block, int max_pairs);
 size_t score_lds_bytes(int lpp, int apl, int max_pairs);
 
 hipError_t launch_map_build(const MapArgs& a, hipStream_t s);
-hipError_t launch_score(const ScoreArgs& a, int lpp, int apl, hipStream_t s);
-hipError_t launch_sample(const SampleArgs& a, int lpp, int apl, int grid, int block, hipStream_t s);
+hipError_t launch_score(const ScoreArgs& a, int lpp, int apl, bool direct, hipStream_t s);
+hipError_t launch_sample(const SampleArgs& a, int lpp, int apl, int grid, int block, bool direct,
+                         hipStream_t s);
 hipError_t launch_best(const BestArgs& a, hipStream_t s);
 hipError_t launch_terms(const TermsArgs& a, int lpp, int apl, int K, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, long long n, uint32_t* out,
                          hipStream_t s);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
 hipError_t launch_add_int(int* p, int v, hipStream_t s);
-int sample_max_blocks_per_cu(int lpp, int apl, int block, size_t lds);
+int sample_max_blocks_per_cu(int lpp, int apl, int block, bool direct, size_t lds);
 
 }  // namespace dock

@@ -117,7 +117,7 @@ size_t sample_lds_bytes(int lpp, int apl, int block, int max_pairs) {
 
 // ================================================================ score
 
-template <int LPP, int APL>
+template <int LPP, int APL, bool DIRECT>
 __global__ void __launch_bounds__(64) score_kernel(ScoreArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int GPB = 64 / LPP;
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(64) score_kernel(ScoreArgs a) {
   wave_sync();
   const float q = r < lg.n_dof ? a.q[pose * a.q_stride + r] : 0.f;
   float xo[APL][3], go[APL][3];
-  const EvalOut o = eval_pose<LPP, APL, true>(L, q, pk.M, pk.grid, gp, S, r, xo, go);
+  const EvalOut o = eval_pose<LPP, APL, true, DIRECT>(L, q, pk, gp, S, r, xo, go);
   if (r == 0) a.E[pose] = o.E;
   if (a.dEdq && r < lg.n_dof) a.dEdq[pose * a.q_stride + r] = o.g;
   if (a.xyz) {
@@ -157,20 +157,27 @@ __global__ void __launch_bounds__(64) score_kernel(ScoreArgs a) {
   }
 }
 
-hipError_t launch_score(const ScoreArgs& a, int lpp, int apl, hipStream_t s) {
+template <bool DIRECT>
+static hipError_t launch_score_t(const ScoreArgs& a, int lpp, int apl, unsigned blocks, size_t lds,
+                                 hipStream_t s) {
+  if (lpp == 16 && apl == 1)
+    hipLaunchKernelGGL((score_kernel<16, 1, DIRECT>), dim3(blocks), dim3(64), lds, s, a);
+  else if (lpp == 32 && apl == 1)
+    hipLaunchKernelGGL((score_kernel<32, 1, DIRECT>), dim3(blocks), dim3(64), lds, s, a);
+  else if (lpp == 64 && apl == 1)
+    hipLaunchKernelGGL((score_kernel<64, 1, DIRECT>), dim3(blocks), dim3(64), lds, s, a);
+  else
+    hipLaunchKernelGGL((score_kernel<64, 2, DIRECT>), dim3(blocks), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_score(const ScoreArgs& a, int lpp, int apl, bool direct, hipStream_t s) {
   const int gpb = 64 / lpp;
   const unsigned blocks = unsigned((a.n_poses + gpb - 1) / gpb);
   const size_t lds = score_lds_bytes(lpp, apl, a.max_pairs);
   if (blocks == 0) return hipSuccess;
-  if (lpp == 16 && apl == 1)
-    hipLaunchKernelGGL((score_kernel<16, 1>), dim3(blocks), dim3(64), lds, s, a);
-  else if (lpp == 32 && apl == 1)
-    hipLaunchKernelGGL((score_kernel<32, 1>), dim3(blocks), dim3(64), lds, s, a);
-  else if (lpp == 64 && apl == 1)
-    hipLaunchKernelGGL((score_kernel<64, 1>), dim3(blocks), dim3(64), lds, s, a);
-  else
-    hipLaunchKernelGGL((score_kernel<64, 2>), dim3(blocks), dim3(64), lds, s, a);
-  return hipGetLastError();
+  return direct ? launch_score_t<true>(a, lpp, apl, blocks, lds, s)
+                : launch_score_t<false>(a, lpp, apl, blocks, lds, s);
 }
 
 // ================================================================ differentiable form
@@ -276,9 +283,9 @@ DK_INLINE float wrap_clamp(float q, int r, const LaneLig<APL>& L) {
   return wrap_angle(q);
 }
 
-template <int LPP, int APL>
-DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const float* M, const GridDev& grid,
-                        const PairRec* pairs, const GroupSlab& S, int lig, int traj, int r) {
+template <int LPP, int APL, bool DIRECT>
+DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const PocketDev& pk, const PairRec* pairs,
+                        const GroupSlab& S, int lig, int traj, int r) {
   const size_t ti = size_t(lig) * a.n_traj + traj;
   const uint32_t k0 = uint32_t(lig), k1 = a.seed;
   const bool dof = r < L.n_dof;
@@ -299,7 +306,7 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const float*
   if (a.init) {
     const uint4 w = philox4x32_10(make_uint4(uint32_t(traj), 0u, 0u, uint32_t(r >> 2)), k0, k1);
     const float q = dof ? L.lo + (L.hi - L.lo) * u01(pick4(w, r & 3)) : 0.f;
-    const EvalOut o = eval_pose<LPP, APL>(L, q, M, grid, pairs, S, r);
+    const EvalOut o = eval_pose<LPP, APL, false, DIRECT>(L, q, pk, pairs, S, r);
     record(q, o.g, o.E);
     if (dof) {
       a.q_cur[ti * qs + r] = q;
@@ -322,21 +329,36 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const float*
     float qn = q;
     if (r == j) qn = L.lo + (L.hi - L.lo) * u01(w.y);
     float E;
-    if (a.local_opt == DOCK_LOCAL_ADAM) {
-      // n_local gradient evaluations with an Adam update after each, then
-      // the energy of the refined pose: one evaluation site, n_local + 1 calls
+    if (a.local_opt != DOCK_LOCAL_LINESEARCH) {
+      // n_local gradient evaluations with a first-order update after each
+      // (Adam by default; the Table S5 alternatives otherwise), then the
+      // energy of the refined pose: one evaluation site, n_local + 1 calls
       float m = 0.f, v = 0.f, b1t = 1.f, b2t = 1.f;
       for (int t = 0;; ++t) {
-        const EvalOut o = eval_pose<LPP, APL>(L, qn, M, grid, pairs, S, r);
+        const EvalOut o = eval_pose<LPP, APL, false, DIRECT>(L, qn, pk, pairs, S, r);
         record(qn, o.g, o.E);
         E = o.E;
         if (t == a.n_local) break;
-        m = a.b1 * m + (1.f - a.b1) * o.g;
-        v = a.b2 * v + (1.f - a.b2) * o.g * o.g;
-        b1t *= a.b1;
-        b2t *= a.b2;
-        const float mh = m / (1.f - b1t), vh = v / (1.f - b2t);
-        if (dof) qn = wrap_clamp(qn - a.lr * mh / (sqrtf(vh) + a.eps), r, L);
+        const float g = o.g;
+        float step;
+        if (a.local_opt == DOCK_LOCAL_SGD) {
+          step = a.lr * g;
+        } else if (a.local_opt == DOCK_LOCAL_RMSPROP) {
+          v = a.rms_alpha * v + (1.f - a.rms_alpha) * g * g;
+          step = a.lr * g / (sqrtf(v) + a.eps);
+        } else if (a.local_opt == DOCK_LOCAL_ADAGRAD) {
+          v += g * g;
+          step = a.lr * g / (sqrtf(v) + a.eps);
+        } else {
+          if (a.local_opt == DOCK_LOCAL_ADAMW) qn *= 1.f - a.lr * a.weight_decay;
+          m = a.b1 * m + (1.f - a.b1) * g;
+          v = a.b2 * v + (1.f - a.b2) * g * g;
+          b1t *= a.b1;
+          b2t *= a.b2;
+          const float mh = m / (1.f - b1t), vh = v / (1.f - b2t);
+          step = a.lr * mh / (sqrtf(vh) + a.eps);
+        }
+        if (dof) qn = wrap_clamp(qn - step, r, L);
       }
     } else {
       // Armijo line search as a loop over trial poses (one evaluation site):
@@ -349,7 +371,7 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const float*
       bool first = true;
       E = 0.f;
       for (;;) {
-        const EvalOut o = eval_pose<LPP, APL>(L, qtry, M, grid, pairs, S, r);
+        const EvalOut o = eval_pose<LPP, APL, false, DIRECT>(L, qtry, pk, pairs, S, r);
         record(qtry, o.g, o.E);
         if (first) {
           E = o.E;
@@ -398,7 +420,7 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const float*
   }
 }
 
-template <int LPP, int APL, int BLOCK>
+template <int LPP, int APL, int BLOCK, bool DIRECT>
 __global__ void __launch_bounds__(BLOCK) sample_kernel(SampleArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int GPB = BLOCK / LPP;
@@ -432,16 +454,16 @@ __global__ void __launch_bounds__(BLOCK) sample_kernel(SampleArgs a) {
       const PocketDev pk = a.pockets[lg.pocket];
       LaneLig<APL> L;
       load_lane_lig<LPP, APL>(L, lg, a.L.ligs + lig, a.L.atoms, a.L.frags, a.L.tors, pk, r);
-      run_traj<LPP, APL>(a, L, pk.M, pk.grid, sp, S, lig, traj, r);
+      run_traj<LPP, APL, DIRECT>(a, L, pk, sp, S, lig, traj, r);
     }
     __syncthreads();
   }
 }
 
-template <int LPP, int APL, int BLOCK>
+template <int LPP, int APL, int BLOCK, bool DIRECT>
 static hipError_t launch_sample_t(const SampleArgs& a, int grid, hipStream_t s) {
   const size_t lds = sample_lds_bytes(LPP, APL, BLOCK, a.max_pairs);
-  hipLaunchKernelGGL((sample_kernel<LPP, APL, BLOCK>), dim3(grid), dim3(BLOCK), lds, s, a);
+  hipLaunchKernelGGL((sample_kernel<LPP, APL, BLOCK, DIRECT>), dim3(grid), dim3(BLOCK), lds, s, a);
   return hipGetLastError();
 }
 
@@ -449,23 +471,25 @@ static hipError_t launch_sample_t(const SampleArgs& a, int grid, hipStream_t s) 
   X(16, 1, 64) X(32, 1, 64) X(64, 1, 64) X(64, 2, 64) X(16, 1, 128) X(32, 1, 128) \
       X(64, 1, 128) X(64, 2, 128) X(16, 1, 256) X(32, 1, 256) X(64, 1, 256) X(64, 2, 256)
 
-hipError_t launch_sample(const SampleArgs& a, int lpp, int apl, int grid, int block, hipStream_t s) {
+hipError_t launch_sample(const SampleArgs& a, int lpp, int apl, int grid, int block, bool direct,
+                         hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-#define X(L, A, B) \
-  if (lpp == L && apl == A && block == B) return launch_sample_t<L, A, B>(a, grid, s);
+#define X(L, A, B)                                                                   \
+  if (lpp == L && apl == A && block == B)                                            \
+    return direct ? launch_sample_t<L, A, B, true>(a, grid, s) : launch_sample_t<L, A, B, false>(a, grid, s);
   DOCK_SAMPLE_CASES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-int sample_max_blocks_per_cu(int lpp, int apl, int block, size_t lds) {
+int sample_max_blocks_per_cu(int lpp, int apl, int block, bool direct, size_t lds) {
   int n = 0;
-#define X(L, A, B)                                                                           \
-  if (lpp == L && apl == A && block == B) {                                                  \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_kernel<L, A, B>, B, lds) != \
-        hipSuccess)                                                                          \
-      n = 1;                                                                                 \
-    return n > 0 ? n : 1;                                                                    \
+#define X(L, A, B)                                                                                 \
+  if (lpp == L && apl == A && block == B) {                                                        \
+    hipError_t e = direct ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_kernel<L, A, B, true>, B, lds) \
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_kernel<L, A, B, false>, B, lds); \
+    if (e != hipSuccess) n = 1;                                                                    \
+    return n > 0 ? n : 1;                                                                          \
   }
   DOCK_SAMPLE_CASES(X)
 #undef X

@@ -255,3 +255,51 @@ def test_autotuner_keeps_random_streams_and_runs(D, mixed):
     st = _state(D, run)
     assert np.all(st["n_evals"] == 1 + 3 * 4) and np.all(np.isfinite(st["E_best"]))
     D.dock_autotune_clear()
+
+
+@pytest.mark.parametrize("opt", ["SGD", "RMSPROP", "ADAGRAD", "ADAMW"])
+def test_optimizer_variants_update_rules(D, opt):
+    """The Table S5 alternatives: every recorded step follows the update rule
+    (FP64 recomputation from the logged gradients), lr 0.02."""
+    pk = tiny_pocket(n=20, radius=6.0, grid=28)
+    L = tiny_ligand(9, 3, seed=6)
+    L.pocket_index = np.zeros(1, np.int32)
+    w = G.weights32(P.PRESET_TRIDS)
+    p = G.load_pocket(pk, P.PRESET_TRIDS, w)
+    H = G.load_ligands(L)
+    T, S, Lc, lr = 8, 3, 4, 0.02
+    kind = getattr(D, "LOCAL_" + opt)
+    G.say("optimizer", opt)
+    run = D.dock_sample(p, H, n_traj=T, n_steps=S, n_local=Lc, seed=2, record_trace=1, local_opt=kind, lr=lr)
+    st = D.dock_run_state(run, trace=True)
+    tr = st["trace"].cpu().numpy()[0]
+    qs = st["q_stride"]
+    n = 6 + H.max_tors
+    topo = topology.from_ligands(L, 0)
+    for t in range(T):
+        for s in range(S):
+            base = 1 + s * (Lc + 1)
+            m = np.zeros(n); v = np.zeros(n)
+            for k in range(Lc):
+                q = tr[t, base + k, :n].astype(np.float64)
+                g = tr[t, base + k, qs:qs + n].astype(np.float64)
+                if opt == "SGD":
+                    step = lr * g
+                elif opt == "RMSPROP":
+                    v = 0.99 * v + 0.01 * g * g
+                    step = lr * g / (np.sqrt(v) + 1e-8)
+                elif opt == "ADAGRAD":
+                    v = v + g * g
+                    step = lr * g / (np.sqrt(v) + 1e-8)
+                else:
+                    q = q * (1 - lr * 0.01)
+                    m = 0.9 * m + 0.1 * g
+                    v = 0.999 * v + 0.001 * g * g
+                    step = lr * (m / (1 - 0.9 ** (k + 1))) / (np.sqrt(v / (1 - 0.999 ** (k + 1))) + 1e-8)
+                nxt = q - step
+                nxt[:3] = np.clip(nxt[:3], topo.box_min, topo.box_max)
+                got = tr[t, base + k + 1, :n]
+                d = np.abs(np.angle(np.exp(1j * (got - nxt))))
+                d[:3] = np.abs(got[:3] - nxt[:3])
+                tol = 2e-4 * (1 + np.abs(step).max()) if opt == "SGD" else 2e-4
+                assert d.max() < tol, (opt, t, s, k, d.max())

@@ -278,3 +278,29 @@ def test_adjoint_exact_in_linear_inputs_and_fd_in_x(preset):
     # q path agrees with the grid scorer's chain rule
     sc = SC.Scorer(pk, preset, weights=w, G=G)
     np.testing.assert_allclose(A["dLdq"], dLdE[:, None] * sc.score(topo, q)["dEdq"], rtol=1e-10, atol=1e-10)
+
+
+@pytest.mark.parametrize("kind", [optim.SGD, optim.RMSPROP, optim.ADAGRAD, optim.ADAMW])
+def test_optimizer_variants_match_torch_fp64(kind):
+    rng = np.random.default_rng(kind)
+    A = rng.normal(size=(7, 7)); A = A @ A.T + np.eye(7)
+    c = rng.normal(size=7) * 0.1
+    f = lambda q: 0.5 * np.einsum("pi,ij,pj->p", q, A, q) + q @ c + 0.1 * (q ** 4).sum(1)
+    df = lambda q: q @ A + c + 0.4 * q ** 3
+    q0 = rng.uniform(-0.3, 0.3, (1, 7))
+    q0[0, :3] = 0.05
+    box = (np.full(3, -100.0), np.full(3, 100.0))
+    q, E = optim.first_order_refine(kind, lambda q: (f(q), df(q)), q0, 8, *box, lr=0.01)
+    t = torch.tensor(q0[0], dtype=torch.float64, requires_grad=True)
+    opt = {optim.SGD: lambda: torch.optim.SGD([t], lr=0.01),
+           optim.RMSPROP: lambda: torch.optim.RMSprop([t], lr=0.01, alpha=0.99, eps=1e-8),
+           optim.ADAGRAD: lambda: torch.optim.Adagrad([t], lr=0.01, eps=1e-8),
+           optim.ADAMW: lambda: torch.optim.AdamW([t], lr=0.01, betas=(0.9, 0.999), eps=1e-8,
+                                                   weight_decay=0.01)}[kind]()
+    At = torch.tensor(A); ct = torch.tensor(c)
+    for _ in range(8):
+        opt.zero_grad()
+        loss = 0.5 * t @ At @ t + t @ ct + 0.1 * (t ** 4).sum()
+        loss.backward()
+        opt.step()
+    np.testing.assert_allclose(q[0], t.detach().numpy(), rtol=1e-12, atol=1e-13)
