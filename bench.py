@@ -191,7 +191,9 @@ def main():
             b = l["bucket"]
             flop = float(np.sum(flops_lig[lb == b])) * (S * (N_LOCAL + 1)) / (1 + S * (N_LOCAL + 1))
             d = per_bucket.setdefault(b, dict(lanes=int(l["lanes_per_pose"]), apl=int(l["atoms_per_lane"]),
-                                              ms=[], flop=flop, ligands=int(np.sum(lb == b))))
+                                              block=int(l["block"]), grid=int(l["grid"]),
+                                              items=int(l["n_items"]), ms=[], flop=flop,
+                                              ligands=int(np.sum(lb == b))))
             d["ms"].append(l["ms"])
     tot_flop = sum(d["flop"] for d in per_bucket.values())
     tot_ms = sum(np.mean(d["ms"]) for d in per_bucket.values())
@@ -199,10 +201,11 @@ def main():
     achieved = dom["flop"] / (np.mean(dom["ms"]) * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=None,
-                    kernel="sample_kernel<%d,%d,256>" % (dom["lanes"], dom["apl"]),
+                    kernel="sample_kernel<%d,%d,%d>" % (dom["lanes"], dom["apl"], dom["block"]),
                     launch_ms=round(float(np.mean(dom["ms"])), 3),
                     all_launches_tflops=round(tot_flop / (tot_ms * 1e-3) / 1e12, 3),
                     buckets=[dict(lanes=d["lanes"], atoms_per_lane=d["apl"], ligands=d["ligands"],
+                                  block=d["block"], grid=d["grid"], work_items=d["items"],
                                   ms=round(float(np.mean(d["ms"])), 3),
                                   tflops=round(d["flop"] / (np.mean(d["ms"]) * 1e-3) / 1e12, 3))
                              for d in per_bucket.values()])

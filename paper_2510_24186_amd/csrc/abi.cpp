@@ -502,9 +502,16 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
       t.b = H.atom_new[H.tors_b[k]];
       tors.push_back(t);
     }
+    // device pair order: chunks of one group's width with spread endpoints
+    std::vector<int> pi_new(H.pair_i.size()), pj_new(H.pair_j.size());
     for (size_t p = 0; p < H.pair_i.size(); ++p) {
-      const int i0 = H.atom_new[H.pair_i[p]], j0 = H.atom_new[H.pair_j[p]];
-      const int ti = H.type[H.pair_i[p]], tj = H.type[H.pair_j[p]];
+      pi_new[p] = H.atom_new[H.pair_i[p]];
+      pj_new[p] = H.atom_new[H.pair_j[p]];
+    }
+    const auto sched = schedule_pairs(H.n_atoms, pi_new, pj_new, lane_cfg(g, 0).lpp);
+    for (const auto& ij : sched) {
+      const int i0 = ij.first, j0 = ij.second;
+      const int ti = H.type[H.dfs_atom[i0]], tj = H.type[H.dfs_atom[j0]];
       const TypePair& tp = tab[ti * kTypes + tj];
       PairRec pr;
       pr.w = uint32_t(i0) | (uint32_t(j0) << 8) | (uint32_t(ti) << 16) | (uint32_t(tj) << 20) |

@@ -120,11 +120,35 @@ struct PairRec {
   float rsum;
 };
 
+// Loads through a pointer known to address global memory.  Pointers read
+// out of device-side structs (the pocket table) are generic to the
+// compiler, which then emits FLAT accesses; those also count against the LDS
+// wait counter, so every later LDS wait of the wave would drain them too.
+template <typename T>
+DK_INLINE T ldg(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+DK_INLINE float4 ldg(const float4* p) {
+  const f32x4_t v = *(const __attribute__((address_space(1))) f32x4_t*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+DK_INLINE float2 ldg(const float2* p) {
+  const f32x2_t v = *(const __attribute__((address_space(1))) f32x2_t*)p;
+  return make_float2(v.x, v.y);
+}
+
 // exp(x) on the hardware exp2 (v_exp_f32): callers pass x * log2(e) already
 // folded into their constants.  Relative error ~1e-6 for the Gaussian
 // arguments used here (|x| < 40).
 DK_INLINE float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+// log2 and 1/x on the hardware units (v_log_f32, v_rcp_f32; about 1 ulp) for
+// normal positive arguments: the clash term only sees d in [0.1, d_clash).
+DK_INLINE float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
+DK_INLINE float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Weighted TRIDS terms (Methods: E_long, E_clash, E_Hbond) at distance d
 // (d2 = d*d): energy and dE/dd.
@@ -142,8 +166,8 @@ DK_INLINE void trids_pair(float d2, float d, float rsum, uint32_t flags, const f
   const float dc = hb ? 2.6f : rsum;
   if (d2 < dc * dc) {
     const float dd = fmaxf(d, 0.1f);
-    e -= w[1] * logf(dd / dc);
-    if (d > 0.1f) de -= w[1] / dd;
+    e -= (w[1] * kLn2) * log2_hw(dd * rcp_hw(dc));
+    if (d > 0.1f) de -= w[1] * rcp_hw(dd);
   }
   if (hb && d2 < 3.4f * 3.4f) {
     const float t = d - 2.88f;
@@ -307,8 +331,9 @@ DK_INLINE Trilerp trilerp(const float* __restrict__ M, const GridDev& g, float p
   const int nx = g.dims[0], nxy = g.dims[0] * g.dims[1];
   t.base = (cz * g.dims[1] + cy) * nx + cx;
   const float* p0 = M + t.base;
-  const float c000 = p0[0], c100 = p0[1], c010 = p0[nx], c110 = p0[nx + 1];
-  const float c001 = p0[nxy], c101 = p0[nxy + 1], c011 = p0[nxy + nx], c111 = p0[nxy + nx + 1];
+  const float c000 = ldg(p0), c100 = ldg(p0 + 1), c010 = ldg(p0 + nx), c110 = ldg(p0 + nx + 1);
+  const float c001 = ldg(p0 + nxy), c101 = ldg(p0 + nxy + 1), c011 = ldg(p0 + nxy + nx),
+              c111 = ldg(p0 + nxy + nx + 1);
   const float fx = t.fx, fy = t.fy, fz = t.fz;
   // interpolate along x, then y, then z
   const float x00 = c000 + fx * (c100 - c000), x10 = c010 + fx * (c110 - c010);
@@ -355,13 +380,13 @@ DK_INLINE void inter_direct(const PocketDev& pk, int preset, const float* w, int
   for (int z = lo[2]; z <= hi[2]; ++z) {
     for (int y = lo[1]; y <= hi[1]; ++y) {
       const int row = z * nxy + y * nx;
-      const int b = pk.cell_start[row + lo[0]], end = pk.cell_start[row + hi[0] + 1];
+      const int b = ldg(pk.cell_start + row + lo[0]), end = ldg(pk.cell_start + row + hi[0] + 1);
       for (int i = b; i < end; ++i) {
-        const float4 rr = pk.rec[i];
+        const float4 rr = ldg(pk.rec + i);
         const float dx = px - rr.x, dy = py - rr.y, dz = pz - rr.z;
         const float d2 = dx * dx + dy * dy + dz * dz;
         if (!(d2 < cut2)) continue;
-        const float2 tp = pk.tp[lt * kTypes + (__float_as_int(rr.w) & 0xff)];
+        const float2 tp = ldg(pk.tp + lt * kTypes + (__float_as_int(rr.w) & 0xff));
         const float inv_d = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
         const float d = d2 * inv_d;
         float ee, de;
@@ -457,6 +482,22 @@ DK_INLINE void load_lane_lig(LaneLig<APL>& L, const LigDev& lg, const LigDev* __
   for (int k = 0; k < kMaxTerms; ++k) L.w[k] = k < pk.n_terms ? pk.w[k] : 0.f;
 }
 
+// Hides the per-lane ligand fields from loop-invariant code motion: inside
+// the sampler's step loop the compiler would otherwise keep every product of
+// them live across evaluations, which costs more registers than recomputing.
+template <int APL>
+DK_INLINE void launder(LaneLig<APL>& L) {
+#pragma unroll
+  for (int s = 0; s < APL; ++s) {
+    asm volatile("" : "+v"(L.ax[s]), "+v"(L.ay[s]), "+v"(L.az[s]));
+    asm volatile("" : "+v"(L.atype[s]), "+v"(L.afrag[s]));
+  }
+  asm volatile("" : "+v"(L.fu[0]), "+v"(L.fu[1]), "+v"(L.fu[2]));
+  asm volatile("" : "+v"(L.fxb[0]), "+v"(L.fxb[1]), "+v"(L.fxb[2]));
+  asm volatile("" : "+v"(L.fparent), "+v"(L.fdof), "+v"(L.tsb), "+v"(L.tse));
+  asm volatile("" : "+v"(L.ta), "+v"(L.tb));
+}
+
 // Per-group LDS slab: coordinates (w = type bits) and intra-pair forces.
 struct GroupSlab {
   float4* xs;  // [LPP*APL]
@@ -480,15 +521,17 @@ struct Rigid {
 // (ceil(log2) rounds of "compose with my current ancestor's transform").
 template <int LPP, int APL>
 DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][3]) {
-  // ---- rigid DOFs to every lane
+  // ---- each lane takes sin/cos of its own angle DOF once; the rigid part
+  // and every fragment's torsion are then fetched from the owning lanes
+  float sq, cq;
+  sincosf(r >= 3 ? q : 0.f, &sq, &cq);
   const float Tx = shfl<LPP>(q, 0), Ty = shfl<LPP>(q, 1), Tz = shfl<LPP>(q, 2);
-  const float al = shfl<LPP>(q, 3), be = shfl<LPP>(q, 4), ga = shfl<LPP>(q, 5);
-  float sa, ca, sb, cb, sg, cg;
-  sincosf(al, &sa, &ca);
-  sincosf(be, &sb, &cb);
-  sincosf(ga, &sg, &cg);
+  const float sa = shfl<LPP>(sq, 3), ca = shfl<LPP>(cq, 3);
+  const float sb = shfl<LPP>(sq, 4), cb = shfl<LPP>(cq, 4);
+  const float sg = shfl<LPP>(sq, 5), cg = shfl<LPP>(cq, 5);
   // ---- fragment transforms: lane f starts from its own local transform
-  const float th = shfl<LPP>(q, L.fdof >= 0 ? L.fdof : 0);
+  const int tsrc = bp_addr<LPP>(L.fdof >= 0 ? L.fdof : 0);
+  const float st = bp(tsrc, sq), ct = bp(tsrc, cq);
   float m[9], t[3];
   int anc = L.fparent;
   if (L.fparent < 0) {
@@ -502,8 +545,6 @@ DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][
     t[2] = Tz;
   } else {
     // Rodrigues rotation about u through xb by theta: y -> B y + (xb - B xb)
-    float st, ct;
-    sincosf(th, &st, &ct);
     const float ux = L.fu[0], uy = L.fu[1], uz = L.fu[2], oc = 1.f - ct;
     m[0] = ct + ux * ux * oc;      m[1] = ux * uy * oc - uz * st; m[2] = ux * uz * oc + uy * st;
     m[3] = uy * ux * oc + uz * st; m[4] = ct + uy * uy * oc;      m[5] = uy * uz * oc - ux * st;
@@ -606,30 +647,31 @@ DK_INLINE float chain_rule(const LaneLig<APL>& L, const Rigid& rg, const float (
       out[k] = a < 0 ? 0.f : (first ? fv : lv);
     }
   };
-  float tot[6];
-  prefix(L.n_atoms, tot);
+  // rigid lanes need the total (prefix at n_atoms minus prefix at 0), torsion
+  // lanes their subtree's range: one pair of prefix lookups serves both
+  const bool rigid = r < 6;
   float pb[6], pe[6];
-  prefix(L.tsb, pb);
-  prefix(L.tse, pe);
-  // axis atoms of this lane's torsion
-  const float4 xa = S.xs[L.ta], xb = S.xs[L.tb];
+  prefix(rigid ? 0 : L.tsb, pb);
+  prefix(rigid ? L.n_atoms : L.tse, pe);
+  float Sg[3], St[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    Sg[k] = pe[k] - pb[k];
+    St[k] = pe[3 + k] - pb[3 + k];
+  }
   // ---- gradient of this lane's DOF
   float gq = 0.f;
   if (r < 3) {
-    gq = tot[r];
+    gq = r == 0 ? Sg[0] : (r == 1 ? Sg[1] : Sg[2]);
   } else if (r == 3) {
-    gq = tot[5];
+    gq = St[2];
   } else if (r == 4) {
-    gq = -sa * tot[3] + ca * tot[4];
+    gq = -sa * St[0] + ca * St[1];
   } else if (r == 5) {
-    gq = ca * cb * tot[3] + sa * cb * tot[4] - sb * tot[5];
+    gq = ca * cb * St[0] + sa * cb * St[1] - sb * St[2];
   } else if (r < L.n_dof) {
-    float Sg[3], St[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      Sg[k] = pe[k] - pb[k];
-      St[k] = pe[3 + k] - pb[3 + k];
-    }
+    // axis atoms of this lane's torsion
+    const float4 xa = S.xs[L.ta], xb = S.xs[L.tb];
     float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
     const float inv = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
     ux *= inv; uy *= inv; uz *= inv;
@@ -643,12 +685,37 @@ DK_INLINE float chain_rule(const LaneLig<APL>& L, const Rigid& rg, const float (
   return gq;
 }
 
+// Energy of one intra-ligand pair and the force f = (dE/dd / d) (x_i - x_j)
+// to add to atom i (and subtract from atom j).
+template <int APL>
+DK_INLINE float pair_force(const LaneLig<APL>& L, const PairRec& pr, const float4& xi, const float4& xj,
+                           float (&f)[3]) {
+  const uint32_t flags = pr.w >> 24;
+  const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+  const float d2 = dx * dx + dy * dy + dz * dz;
+  // 1/d from the hardware reciprocal square root; d = d2 / d
+  const float inv_d = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
+  const float d = d2 * inv_d;
+  float e, de;
+  if (L.preset == DOCK_PRESET_TRIDS)
+    trids_pair(d2, d, pr.rsum, flags, L.w, e, de);
+  else
+    vina_pair(d2, d, pr.rsum, flags, L.w, e, de);
+  const float c = de * inv_d;
+  f[0] = c * dx;
+  f[1] = c * dy;
+  f[2] = c * dz;
+  return e;
+}
+
 // One evaluation of E and dE/dq at the pose whose DOF r is held by lane r.
 // Optionally leaves world coordinates and atom gradients in xo/go.
 template <int LPP, int APL, bool WANT_X = false, bool DIRECT = false>
-DK_INLINE EvalOut eval_pose(const LaneLig<APL>& L, float q, const PocketDev& pk,
+DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& pk,
                             const PairRec* __restrict__ pairs, const GroupSlab& S, int r,
                             float (*xo)[3] = nullptr, float (*go)[3] = nullptr) {
+  LaneLig<APL> L = Lin;
+  launder(L);
   // ---- atoms: place, interpolate, publish coordinates to the slab
   float x[APL][3], g[APL][3];
   const Rigid rg = fk_place<LPP, APL>(L, q, r, x);
@@ -679,32 +746,46 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& L, float q, const PocketDev& pk,
     }
   }
   wave_sync();
-  // ---- intra-ligand pairs, strided over the group's lanes
-  for (int p = r; p < L.n_pairs; p += LPP) {
-    const PairRec pr = pairs[p];
-    const int i = pr.w & 0xff, j = (pr.w >> 8) & 0xff;
-    const uint32_t flags = pr.w >> 24;
-    const float4 xi = S.xs[i], xj = S.xs[j];
-    const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-    const float d2 = dx * dx + dy * dy + dz * dz;
-    // 1/d from the hardware reciprocal square root; d = d2 / d
-    const float inv_d = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
-    const float d = d2 * inv_d;
-    float e, de;
-    if (L.preset == DOCK_PRESET_TRIDS)
-      trids_pair(d2, d, pr.rsum, flags, L.w, e, de);
-    else
-      vina_pair(d2, d, pr.rsum, flags, L.w, e, de);
-    e_lane += e;
-    if (de != 0.f) {
-      const float c = de * inv_d;
-      const float fx = c * dx, fy = c * dy, fz = c * dz;
-      atomicAdd(&S.fx[i], fx);
-      atomicAdd(&S.fy[i], fy);
-      atomicAdd(&S.fz[i], fz);
-      atomicAdd(&S.fx[j], -fx);
-      atomicAdd(&S.fy[j], -fy);
-      atomicAdd(&S.fz[j], -fz);
+  // ---- intra-ligand pairs: lane r takes pairs r, r + LPP, r + 2 LPP, ...
+  // two per pass, with the next pass's records read before this pass's
+  // arithmetic so that LDS latency overlaps it
+  const int np = L.n_pairs;
+  if (r < np) {
+    int p = r;
+    PairRec a0 = pairs[p], a1 = pairs[p + LPP < np ? p + LPP : p];
+    for (;;) {
+      const bool two = p + LPP < np;
+      const int i0 = a0.w & 0xff, j0 = (a0.w >> 8) & 0xff;
+      const int i1 = a1.w & 0xff, j1 = (a1.w >> 8) & 0xff;
+      const float4 xi0 = S.xs[i0], xj0 = S.xs[j0], xi1 = S.xs[i1], xj1 = S.xs[j1];
+      const int pn = p + 2 * LPP;
+      const bool more = pn < np;
+      const int q0 = more ? pn : p;
+      const PairRec b0 = pairs[q0], b1 = pairs[q0 + LPP < np ? q0 + LPP : q0];
+      float f0[3], f1[3];
+      const float e0 = pair_force(L, a0, xi0, xj0, f0);
+      const float e1 = pair_force(L, a1, xi1, xj1, f1);
+      e_lane += two ? e0 + e1 : e0;
+      if (f0[0] != 0.f || f0[1] != 0.f || f0[2] != 0.f) {
+        atomicAdd(&S.fx[i0], f0[0]);
+        atomicAdd(&S.fy[i0], f0[1]);
+        atomicAdd(&S.fz[i0], f0[2]);
+        atomicAdd(&S.fx[j0], -f0[0]);
+        atomicAdd(&S.fy[j0], -f0[1]);
+        atomicAdd(&S.fz[j0], -f0[2]);
+      }
+      if (two && (f1[0] != 0.f || f1[1] != 0.f || f1[2] != 0.f)) {
+        atomicAdd(&S.fx[i1], f1[0]);
+        atomicAdd(&S.fy[i1], f1[1]);
+        atomicAdd(&S.fz[i1], f1[2]);
+        atomicAdd(&S.fx[j1], -f1[0]);
+        atomicAdd(&S.fy[j1], -f1[1]);
+        atomicAdd(&S.fz[j1], -f1[2]);
+      }
+      if (!more) break;
+      a0 = b0;
+      a1 = b1;
+      p = pn;
     }
   }
   wave_sync();

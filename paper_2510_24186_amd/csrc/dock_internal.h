@@ -110,6 +110,16 @@ int prepare_ligand(int n, const uint8_t* element, const uint8_t* n_h, const floa
                    const float* box_min, const float* box_max, LigandHost& out, std::string& err);
 
 void type_pair_table(int preset, TypePair table[kTypes * kTypes]);
+
+// Orders and orients the pair list (atom indices in any numbering) for lanes
+// that take `chunk` consecutive pairs at a time and scatter forces to both
+// endpoints with LDS atomics: within each chunk an atom is first endpoint of
+// as few pairs as the greedy fill can manage, and likewise second endpoint,
+// so the two atomic adds of a chunk rarely hit one address from many lanes.
+// Returns the oriented pairs; every input pair appears exactly once.
+std::vector<std::pair<int, int>> schedule_pairs(int n_atoms, const std::vector<int>& pi,
+                                                const std::vector<int>& pj, int chunk);
+
 void preset_weights(int preset, float* w, int* K);
 
 }  // namespace dock

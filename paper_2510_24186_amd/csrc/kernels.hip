@@ -19,6 +19,16 @@ namespace dock {
 
 // ================================================================ maps
 
+// ((dx*dx + dy*dy) + dz*dz) with every operation rounded separately.  The
+// default contraction would fuse a product into the following sum (one
+// rounding fewer), which moves d2 by an ulp and flips cutoff decisions that
+// sit on the boundary.
+__device__ __forceinline__ float d2_rounded(float dx, float dy, float dz) {
+#pragma clang fp contract(off)
+  const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+  return (xx + yy) + zz;
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) map_kernel(MapArgs a) {
   __shared__ float4 tile[256];
@@ -47,10 +57,9 @@ __global__ void __launch_bounds__(256) map_kernel(MapArgs a) {
     if (!live) continue;
     for (int j = 0; j < cnt; ++j) {
       const float4 rj = tile[j];
-      // FP32 squared distance in a fixed order, no contraction: the
-      // inside-cutoff decisions depend on these exact bits.
-      const float dx = __fsub_rn(px, rj.x), dy = __fsub_rn(py, rj.y), dz = __fsub_rn(pz, rj.z);
-      const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+      // FP32 squared distance in a fixed order, each product and sum rounded
+      // on its own: the inside-cutoff decisions depend on these exact bits
+      const float d2 = d2_rounded(px - rj.x, py - rj.y, pz - rj.z);
       if (!(d2 < cmax2)) continue;
       const double ex = double(px) - double(rj.x), ey = double(py) - double(rj.y),
                    ez = double(pz) - double(rj.z);
@@ -420,8 +429,10 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const Pocket
   }
 }
 
+// Three waves per SIMD: the register budget (168) that the step loop fits
+// without spilling.
 template <int LPP, int APL, int BLOCK, bool DIRECT>
-__global__ void __launch_bounds__(BLOCK) sample_kernel(SampleArgs a) {
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) sample_kernel(SampleArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int GPB = BLOCK / LPP;
   const int grp = threadIdx.x / LPP, r = threadIdx.x % LPP;

@@ -282,3 +282,45 @@ int prepare_ligand(int n, const uint8_t* element, const uint8_t* n_h, const floa
 }
 
 }  // namespace dock
+
+namespace dock {
+
+std::vector<std::pair<int, int>> schedule_pairs(int n_atoms, const std::vector<int>& pi,
+                                                const std::vector<int>& pj, int chunk) {
+  const size_t P = pi.size();
+  std::vector<std::pair<int, int>> out;
+  out.reserve(P);
+  std::vector<char> used(P, 0);
+  std::vector<int> ci(n_atoms), cj(n_atoms);
+  size_t first_free = 0;
+  while (out.size() < P) {
+    std::fill(ci.begin(), ci.end(), 0);
+    std::fill(cj.begin(), cj.end(), 0);
+    const size_t take = std::min<size_t>(size_t(chunk), P - out.size());
+    size_t placed = 0;
+    // level-by-level fill: first pairs whose endpoints are still unused in
+    // this chunk (in either orientation), then those at multiplicity 1, ...
+    for (int level = 1; placed < take; ++level) {
+      while (first_free < P && used[first_free]) ++first_free;
+      for (size_t p = first_free; p < P && placed < take; ++p) {
+        if (used[p]) continue;
+        const int a = pi[p], b = pj[p];
+        int u = -1, v = -1;
+        if (ci[a] < level && cj[b] < level) {
+          u = a; v = b;
+        } else if (ci[b] < level && cj[a] < level) {
+          u = b; v = a;
+        }
+        if (u < 0) continue;
+        ++ci[u];
+        ++cj[v];
+        used[p] = 1;
+        out.emplace_back(u, v);
+        ++placed;
+      }
+    }
+  }
+  return out;
+}
+
+}  // namespace dock
