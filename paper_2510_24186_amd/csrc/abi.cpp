@@ -502,26 +502,46 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
       t.b = H.atom_new[H.tors_b[k]];
       tors.push_back(t);
     }
-    // device pair order: chunks of one group's width with spread endpoints
+    // device pair records: with one atom per lane, passes of one group's
+    // width whose forces are gathered per atom (no LDS atomics); with two
+    // atoms per lane, the caller's order, strided over the lanes
     std::vector<int> pi_new(H.pair_i.size()), pj_new(H.pair_j.size());
     for (size_t p = 0; p < H.pair_i.size(); ++p) {
       pi_new[p] = H.atom_new[H.pair_i[p]];
       pj_new[p] = H.atom_new[H.pair_j[p]];
     }
-    const auto sched = schedule_pairs(H.n_atoms, pi_new, pj_new, lane_cfg(g, 0).lpp);
-    for (const auto& ij : sched) {
-      const int i0 = ij.first, j0 = ij.second;
+    auto record = [&](int i0, int j0) {
+      PairRec pr{};
+      if (i0 < 0) {
+        pr.w = kPairEmpty;
+        return pr;
+      }
       const int ti = H.type[H.dfs_atom[i0]], tj = H.type[H.dfs_atom[j0]];
       const TypePair& tp = tab[ti * kTypes + tj];
-      PairRec pr;
       pr.w = uint32_t(i0) | (uint32_t(j0) << 8) | (uint32_t(ti) << 16) | (uint32_t(tj) << 20) |
              (tp.flags << 24);
       pr.rsum = tp.rsum;
-      pairs.push_back(pr);
+      return pr;
+    };
+    const LaneCfg lc = lane_cfg(g, 0);
+    if (lc.apl == 1 && !pi_new.empty()) {
+      const PassPlan plan = schedule_passes(H.n_atoms, pi_new, pj_new, lc.lpp);
+      g.n_pass = plan.n_pass;
+      g.pass_w = lc.lpp;
+      g.pull_cap = plan.cap;
+      for (size_t s = 0; s < plan.slot_i.size(); ++s) {
+        PairRec pr = record(plan.slot_i[s], plan.slot_j[s]);
+        pr.pull_lo = uint32_t(plan.pulls[s]);
+        pr.pull_hi = uint32_t(plan.pulls[s] >> 32);
+        pairs.push_back(pr);
+      }
+    } else {
+      for (size_t p = 0; p < pi_new.size(); ++p) pairs.push_back(record(pi_new[p], pj_new[p]));
     }
+    g.n_prec = int(pairs.size()) - g.pair_off;
     L->max_atoms = std::max(L->max_atoms, H.n_atoms);
     L->max_tors = std::max(L->max_tors, H.n_tors);
-    L->max_pairs = std::max(L->max_pairs, g.n_pairs);
+    L->max_pairs = std::max(L->max_pairs, g.n_prec);
     L->max_frags = std::max(L->max_frags, H.n_frags);
     L->total_atoms += H.n_atoms;
   }
@@ -932,7 +952,7 @@ static hipError_t enqueue_phase(dock_run_s* r, bool init, int steps, hipStream_t
         a.items = r->d_items + r->lig_item_off[l];
         a.n_items = r->lig_n_items[l];
         a.queue = nullptr;
-        a.max_pairs = r->L->h_ligs[l].n_pairs;
+        a.max_pairs = r->L->h_ligs[l].n_prec;
         e = timed_launch(r, a, r->lig_bucket[l], B.lpp, B.apl, r->lig_n_items[l], B.block, s);
         if (e != hipSuccess) return e;
       }
@@ -1076,7 +1096,7 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
     }
     Bucket& B = r->buckets[it->second];
     B.ligs.push_back(l);
-    B.max_pairs = std::max(B.max_pairs, L->h_ligs[l].n_pairs);
+    B.max_pairs = std::max(B.max_pairs, L->h_ligs[l].n_prec);
     r->lig_bucket[l] = it->second;
   }
   std::vector<int2> items;

@@ -113,11 +113,15 @@ DK_INLINE float group_scan(float v) {
 
 // ------------------------------------------------------------------ terms
 // Pair word: i | j << 8 | type_i << 16 | type_j << 20 | flags << 24, plus the
-// radius sum as a float in the second word.  flags bit0 donor/acceptor pair,
-// bit1 both hydrophobic.
-struct PairRec {
+// radius sum as a float.  flags bit0 donor/acceptor pair, bit1 both
+// hydrophobic, bit7 empty slot (no pair).  In the pass layout the record of
+// slot s also carries, in pull, the pull list of atom s for that pass (see
+// PassPlan); it is zero otherwise.
+constexpr uint32_t kPairEmpty = 0x80u << 24;
+struct alignas(16) PairRec {
   uint32_t w;
   float rsum;
+  uint32_t pull_lo, pull_hi;
 };
 
 // Loads through a pointer known to address global memory.  Pointers read
@@ -408,7 +412,8 @@ DK_INLINE void inter_direct(const PocketDev& pk, int preset, const float* w, int
 // Static per-ligand data held in registers by each lane of a group.
 template <int APL>
 struct LaneLig {
-  int n_atoms, n_frags, n_dof, n_pairs, fk_rounds, preset;
+  int n_atoms, n_frags, n_dof, n_prec, fk_rounds, preset;
+  int n_pass, pass_w, pull_cap;  // pass layout of the pair records (n_pass = 0: strided)
   // atoms owned by this lane
   float ax[APL], ay[APL], az[APL];
   int atype[APL], afrag[APL], aorig[APL];
@@ -428,7 +433,10 @@ DK_INLINE void load_lane_lig(LaneLig<APL>& L, const LigDev& lg, const LigDev* __
   L.n_atoms = lg.n_atoms;
   L.n_frags = lg.n_frags;
   L.n_dof = lg.n_dof;
-  L.n_pairs = lg.n_pairs;
+  L.n_prec = lg.n_prec;
+  L.n_pass = lg.n_pass;
+  L.pass_w = lg.pass_w;
+  L.pull_cap = lg.pull_cap;
   L.fk_rounds = lg.fk_rounds;
   L.preset = pk.preset;
 #pragma unroll
@@ -498,12 +506,17 @@ DK_INLINE void launder(LaneLig<APL>& L) {
   asm volatile("" : "+v"(L.ta), "+v"(L.tb));
 }
 
-// Per-group LDS slab: coordinates (w = type bits) and intra-pair forces.
+// Per-group LDS slab: coordinates (w = type bits), then either per-atom
+// intra-pair force sums (strided pairs, LDS atomics) or, in the pass layout,
+// one force per pair slot (plain stores, gathered per atom).
+// The per-atom sums are FP64: on gfx950 an FP32 LDS atomic add is executed
+// one lane at a time (~3 cycles per active lane), an FP64 one at full rate.
 struct GroupSlab {
-  float4* xs;  // [LPP*APL]
-  float* fx;   // [LPP*APL]
-  float* fy;
-  float* fz;
+  float4* xs;   // [LPP*APL]
+  double* fx;   // [LPP*APL]
+  double* fy;
+  double* fz;
+  float4* fb;   // [LPP], aliases fx/fy/fz
 };
 
 struct EvalOut {
@@ -738,65 +751,89 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
         g[s][2] = tl.gz;
       }
       S.xs[atom] = make_float4(x[s][0], x[s][1], x[s][2], 0.f);
-      S.fx[atom] = 0.f;
-      S.fy[atom] = 0.f;
-      S.fz[atom] = 0.f;
     } else {
       g[s][0] = g[s][1] = g[s][2] = 0.f;
     }
   }
   wave_sync();
-  // ---- intra-ligand pairs: lane r takes pairs r, r + LPP, r + 2 LPP, ...
-  // two per pass, with the next pass's records read before this pass's
-  // arithmetic so that LDS latency overlaps it
-  const int np = L.n_pairs;
-  if (r < np) {
-    int p = r;
-    PairRec a0 = pairs[p], a1 = pairs[p + LPP < np ? p + LPP : p];
-    for (;;) {
-      const bool two = p + LPP < np;
-      const int i0 = a0.w & 0xff, j0 = (a0.w >> 8) & 0xff;
-      const int i1 = a1.w & 0xff, j1 = (a1.w >> 8) & 0xff;
-      const float4 xi0 = S.xs[i0], xj0 = S.xs[j0], xi1 = S.xs[i1], xj1 = S.xs[j1];
-      const int pn = p + 2 * LPP;
-      const bool more = pn < np;
-      const int q0 = more ? pn : p;
-      const PairRec b0 = pairs[q0], b1 = pairs[q0 + LPP < np ? q0 + LPP : q0];
-      float f0[3], f1[3];
-      const float e0 = pair_force(L, a0, xi0, xj0, f0);
-      const float e1 = pair_force(L, a1, xi1, xj1, f1);
-      e_lane += two ? e0 + e1 : e0;
-      if (f0[0] != 0.f || f0[1] != 0.f || f0[2] != 0.f) {
-        atomicAdd(&S.fx[i0], f0[0]);
-        atomicAdd(&S.fy[i0], f0[1]);
-        atomicAdd(&S.fz[i0], f0[2]);
-        atomicAdd(&S.fx[j0], -f0[0]);
-        atomicAdd(&S.fy[j0], -f0[1]);
-        atomicAdd(&S.fz[j0], -f0[2]);
+  float fsum[APL][3];
+#pragma unroll
+  for (int s = 0; s < APL; ++s) fsum[s][0] = fsum[s][1] = fsum[s][2] = 0.f;
+  if (APL == 1 && L.n_pass > 0) {
+    // ---- pass layout: lane r evaluates slot r of every pass, stores the
+    // pair force in its slot, then gathers the slots listed for its atom
+    const int W = L.pass_w;
+    for (int ps = 0; ps < L.n_pass; ++ps) {
+      const int slot = ps * W + r;
+      const PairRec pr = pairs[r < W ? slot : ps * W];
+      float f[3] = {0.f, 0.f, 0.f};
+      if (r < W && !(pr.w & kPairEmpty)) {
+        const int i = pr.w & 0xff, j = (pr.w >> 8) & 0xff;
+        e_lane += pair_force(L, pr, S.xs[i], S.xs[j], f);
       }
-      if (two && (f1[0] != 0.f || f1[1] != 0.f || f1[2] != 0.f)) {
-        atomicAdd(&S.fx[i1], f1[0]);
-        atomicAdd(&S.fy[i1], f1[1]);
-        atomicAdd(&S.fz[i1], f1[2]);
-        atomicAdd(&S.fx[j1], -f1[0]);
-        atomicAdd(&S.fy[j1], -f1[1]);
-        atomicAdd(&S.fz[j1], -f1[2]);
+      if (r < W) S.fb[r] = make_float4(f[0], f[1], f[2], 0.f);
+      wave_sync();
+      uint32_t lo = r < W ? pr.pull_lo : 0u, hi = r < W ? pr.pull_hi : 0u;
+      for (int c = 0; c < L.pull_cap; ++c) {
+        const uint32_t e = lo & 0xffu;
+        lo = (lo >> 8) | (hi << 24);
+        hi >>= 8;
+        if (e & 0x80u) {
+          const float4 v = S.fb[e & 0x3fu];
+          const float sg = (e & 0x40u) ? -1.f : 1.f;
+          fsum[0][0] += sg * v.x;
+          fsum[0][1] += sg * v.y;
+          fsum[0][2] += sg * v.z;
+        }
       }
-      if (!more) break;
-      a0 = b0;
-      a1 = b1;
-      p = pn;
+      wave_sync();
+    }
+  } else {
+    // ---- strided: lane r takes records r, r + LPP, ...; forces by LDS atomics
+#pragma unroll
+    for (int s = 0; s < APL; ++s) {
+      const int atom = APL * r + s;
+      if (atom < L.n_atoms) {
+        S.fx[atom] = 0.0;
+        S.fy[atom] = 0.0;
+        S.fz[atom] = 0.0;
+      }
+    }
+    wave_sync();
+    for (int p = r; p < L.n_prec; p += LPP) {
+      const PairRec pr = pairs[p];
+      if (pr.w & kPairEmpty) continue;
+      const int i = pr.w & 0xff, j = (pr.w >> 8) & 0xff;
+      float f[3];
+      e_lane += pair_force(L, pr, S.xs[i], S.xs[j], f);
+      if (f[0] != 0.f || f[1] != 0.f || f[2] != 0.f) {
+        atomicAdd(&S.fx[i], double(f[0]));
+        atomicAdd(&S.fy[i], double(f[1]));
+        atomicAdd(&S.fz[i], double(f[2]));
+        atomicAdd(&S.fx[j], -double(f[0]));
+        atomicAdd(&S.fy[j], -double(f[1]));
+        atomicAdd(&S.fz[j], -double(f[2]));
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < APL; ++s) {
+      const int atom = APL * r + s;
+      if (atom < L.n_atoms) {
+        fsum[s][0] = float(S.fx[atom]);
+        fsum[s][1] = float(S.fy[atom]);
+        fsum[s][2] = float(S.fz[atom]);
+      }
     }
   }
-  wave_sync();
   // ---- per-atom total gradient: add the intra-pair forces
 #pragma unroll
   for (int s = 0; s < APL; ++s) {
     const int atom = APL * r + s;
     if (atom < L.n_atoms) {
-      g[s][0] += S.fx[atom];
-      g[s][1] += S.fy[atom];
-      g[s][2] += S.fz[atom];
+      g[s][0] += fsum[s][0];
+      g[s][1] += fsum[s][1];
+      g[s][2] += fsum[s][2];
     }
     if (WANT_X) {
       xo[s][0] = x[s][0]; xo[s][1] = x[s][1]; xo[s][2] = x[s][2];
@@ -867,14 +904,15 @@ DK_INLINE float eval_terms(const LaneLig<APL>& L, float q, float (&x)[APL][3], f
         }
       }
       S.xs[atom] = make_float4(x[s][0], x[s][1], x[s][2], 0.f);
-      S.fx[atom] = 0.f;
-      S.fy[atom] = 0.f;
-      S.fz[atom] = 0.f;
+      S.fx[atom] = 0.0;
+      S.fy[atom] = 0.0;
+      S.fz[atom] = 0.0;
     }
   }
   wave_sync();
-  for (int p = r; p < L.n_pairs; p += LPP) {
+  for (int p = r; p < L.n_prec; p += LPP) {
     const PairRec pr = pairs[p];
+    if (pr.w & kPairEmpty) continue;
     const int i = pr.w & 0xff, j = (pr.w >> 8) & 0xff;
     const float4 xi = S.xs[i], xj = S.xs[j];
     const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
@@ -890,12 +928,12 @@ DK_INLINE float eval_terms(const LaneLig<APL>& L, float q, float (&x)[APL][3], f
     }
     if (de != 0.f && d > 0.f) {
       const float c = de / d;
-      atomicAdd(&S.fx[i], c * dx);
-      atomicAdd(&S.fy[i], c * dy);
-      atomicAdd(&S.fz[i], c * dz);
-      atomicAdd(&S.fx[j], -c * dx);
-      atomicAdd(&S.fy[j], -c * dy);
-      atomicAdd(&S.fz[j], -c * dz);
+      atomicAdd(&S.fx[i], double(c * dx));
+      atomicAdd(&S.fy[i], double(c * dy));
+      atomicAdd(&S.fz[i], double(c * dz));
+      atomicAdd(&S.fx[j], -double(c * dx));
+      atomicAdd(&S.fy[j], -double(c * dy));
+      atomicAdd(&S.fz[j], -double(c * dz));
     }
   }
   wave_sync();
@@ -903,9 +941,9 @@ DK_INLINE float eval_terms(const LaneLig<APL>& L, float q, float (&x)[APL][3], f
   for (int s = 0; s < APL; ++s) {
     const int atom = APL * r + s;
     if (atom < L.n_atoms) {
-      g[s][0] += S.fx[atom];
-      g[s][1] += S.fy[atom];
-      g[s][2] += S.fz[atom];
+      g[s][0] += float(S.fx[atom]);
+      g[s][1] += float(S.fy[atom]);
+      g[s][2] += float(S.fz[atom]);
     }
   }
   float E = group_sum<LPP>(eout);

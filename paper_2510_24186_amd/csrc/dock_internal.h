@@ -23,11 +23,12 @@ constexpr int kMaxTerms = DOCK_MAX_TERMS;
 struct alignas(16) LigDev {
   int n_atoms, n_tors, n_frags, n_pairs;
   int atom_off, pair_off, frag_off, tors_off;
-  int pocket, fk_rounds, n_dof, pad0;
+  int pocket, fk_rounds, n_dof, n_prec;   // n_prec: device pair records (with empty slots)
   float c0[3];
   float box_min[3];
   float box_max[3];
-  float pad1[3];
+  int n_pass, pass_w, pull_off;           // pass layout (n_pass = 0: pairs are strided, forces by atomics)
+  int pull_cap;                           // entries per pull list
 };
 
 // Fragment record (DFS numbering).  Root: parent = -1, dof = -1.
@@ -111,14 +112,22 @@ int prepare_ligand(int n, const uint8_t* element, const uint8_t* n_h, const floa
 
 void type_pair_table(int preset, TypePair table[kTypes * kTypes]);
 
-// Orders and orients the pair list (atom indices in any numbering) for lanes
-// that take `chunk` consecutive pairs at a time and scatter forces to both
-// endpoints with LDS atomics: within each chunk an atom is first endpoint of
-// as few pairs as the greedy fill can manage, and likewise second endpoint,
-// so the two atomic adds of a chunk rarely hit one address from many lanes.
-// Returns the oriented pairs; every input pair appears exactly once.
-std::vector<std::pair<int, int>> schedule_pairs(int n_atoms, const std::vector<int>& pi,
-                                                const std::vector<int>& pj, int chunk);
+// Intra-pair passes for groups whose lanes each own one atom.  A pass is
+// `width` slots (one per lane); slot s of pass k holds pair
+// (slot_i, slot_j)[k * width + s], or -1 for an empty slot.  Every pair is in
+// exactly one slot, and no atom is an endpoint of more than `cap` slots of a
+// pass.  pulls[k * width + a] lists those slots for atom a: byte c is
+// 0x80 | slot when atom a is the pair's first endpoint (the force is added),
+// 0xC0 | slot when it is the second (subtracted), 0 past the end of the list.
+// Lanes write their slot's force to LDS with plain stores and each atom lane
+// then gathers its own entries: no LDS atomics.
+constexpr int kMaxPull = 8;
+struct PassPlan {
+  int n_pass = 0, cap = 0;
+  std::vector<int> slot_i, slot_j;
+  std::vector<uint64_t> pulls;
+};
+PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vector<int>& pj, int width);
 
 void preset_weights(int preset, float* w, int* K);
 

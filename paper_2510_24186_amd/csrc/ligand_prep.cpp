@@ -285,42 +285,69 @@ int prepare_ligand(int n, const uint8_t* element, const uint8_t* n_h, const floa
 
 namespace dock {
 
-std::vector<std::pair<int, int>> schedule_pairs(int n_atoms, const std::vector<int>& pi,
-                                                const std::vector<int>& pj, int chunk) {
+PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vector<int>& pj, int width) {
+  PassPlan plan;
   const size_t P = pi.size();
-  std::vector<std::pair<int, int>> out;
-  out.reserve(P);
+  if (P == 0) return plan;
+  std::vector<int> deg(n_atoms, 0);
+  for (size_t p = 0; p < P; ++p) {
+    ++deg[pi[p]];
+    ++deg[pj[p]];
+  }
+  const int max_deg = *std::max_element(deg.begin(), deg.end());
+  const int passes0 = int((P + width - 1) / width);
+  // incidences one atom may take per pass: enough for a full pass on
+  // average (2 * width / n_atoms) and for the busiest atom to finish within
+  // the minimal pass count, plus one of slack; at most kMaxPull
+  int cap = std::max((2 * width + n_atoms - 1) / n_atoms, (max_deg + passes0 - 1) / passes0) + 1;
+  cap = std::min(cap, kMaxPull);
+  // pairs touching busy atoms first, so that hubs spread over every pass
+  std::vector<int> order(P);
+  for (size_t p = 0; p < P; ++p) order[p] = int(p);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return std::max(deg[pi[a]], deg[pj[a]]) > std::max(deg[pi[b]], deg[pj[b]]);
+  });
   std::vector<char> used(P, 0);
-  std::vector<int> ci(n_atoms), cj(n_atoms);
-  size_t first_free = 0;
-  while (out.size() < P) {
-    std::fill(ci.begin(), ci.end(), 0);
-    std::fill(cj.begin(), cj.end(), 0);
-    const size_t take = std::min<size_t>(size_t(chunk), P - out.size());
-    size_t placed = 0;
-    // level-by-level fill: first pairs whose endpoints are still unused in
-    // this chunk (in either orientation), then those at multiplicity 1, ...
-    for (int level = 1; placed < take; ++level) {
-      while (first_free < P && used[first_free]) ++first_free;
-      for (size_t p = first_free; p < P && placed < take; ++p) {
-        if (used[p]) continue;
-        const int a = pi[p], b = pj[p];
-        int u = -1, v = -1;
-        if (ci[a] < level && cj[b] < level) {
-          u = a; v = b;
-        } else if (ci[b] < level && cj[a] < level) {
-          u = b; v = a;
-        }
-        if (u < 0) continue;
-        ++ci[u];
-        ++cj[v];
-        used[p] = 1;
-        out.emplace_back(u, v);
-        ++placed;
-      }
+  std::vector<int> cnt(n_atoms);
+  size_t placed = 0, first_free = 0;
+  while (placed < P) {
+    std::fill(cnt.begin(), cnt.end(), 0);
+    const size_t base = plan.slot_i.size();
+    plan.slot_i.resize(base + width, -1);
+    plan.slot_j.resize(base + width, -1);
+    int fill = 0;
+    while (first_free < P && used[order[first_free]]) ++first_free;
+    for (size_t k = first_free; k < P && fill < width; ++k) {
+      const int p = order[k];
+      if (used[p]) continue;
+      const int a = pi[p], b = pj[p];
+      if (cnt[a] >= cap || cnt[b] >= cap) continue;
+      ++cnt[a];
+      ++cnt[b];
+      used[p] = 1;
+      plan.slot_i[base + fill] = a;
+      plan.slot_j[base + fill] = b;
+      ++fill;
+      ++placed;
+    }
+    ++plan.n_pass;
+  }
+  plan.cap = cap;
+  // pull lists: per pass and atom, the slots that hold its pairs
+  plan.pulls.assign(size_t(plan.n_pass) * width, 0ull);
+  std::vector<int> k_of(n_atoms);
+  for (int ps = 0; ps < plan.n_pass; ++ps) {
+    std::fill(k_of.begin(), k_of.end(), 0);
+    for (int s = 0; s < width; ++s) {
+      const int a = plan.slot_i[size_t(ps) * width + s], b = plan.slot_j[size_t(ps) * width + s];
+      if (a < 0) continue;
+      uint64_t& la = plan.pulls[size_t(ps) * width + a];
+      uint64_t& lb = plan.pulls[size_t(ps) * width + b];
+      la |= uint64_t(0x80u | unsigned(s)) << (8 * k_of[a]++);
+      lb |= uint64_t(0xC0u | unsigned(s)) << (8 * k_of[b]++);
     }
   }
-  return out;
+  return plan;
 }
 
 }  // namespace dock
