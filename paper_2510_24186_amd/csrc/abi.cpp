@@ -529,19 +529,23 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
       g.n_pass = plan.n_pass;
       g.pass_w = lc.lpp;
       g.pull_cap = plan.cap;
-      for (size_t s = 0; s < plan.slot_i.size(); ++s) {
-        PairRec pr = record(plan.slot_i[s], plan.slot_j[s]);
-        pr.pull_lo = uint32_t(plan.pulls[s]);
-        pr.pull_hi = uint32_t(plan.pulls[s] >> 32);
-        pairs.push_back(pr);
+      for (size_t s = 0; s < plan.slot_i.size(); ++s) pairs.push_back(record(plan.slot_i[s], plan.slot_j[s]));
+      for (size_t s = 0; s < plan.pulls.size(); ++s) {
+        PairRec pw;
+        pw.w = uint32_t(plan.pulls[s]);
+        const uint32_t hi = uint32_t(plan.pulls[s] >> 32);
+        std::memcpy(&pw.rsum, &hi, 4);
+        pairs.push_back(pw);
       }
+      g.n_prec = int(plan.slot_i.size());
     } else {
       for (size_t p = 0; p < pi_new.size(); ++p) pairs.push_back(record(pi_new[p], pj_new[p]));
+      g.n_prec = int(pi_new.size());
     }
-    g.n_prec = int(pairs.size()) - g.pair_off;
+    g.n_stage = int(pairs.size()) - g.pair_off;
     L->max_atoms = std::max(L->max_atoms, H.n_atoms);
     L->max_tors = std::max(L->max_tors, H.n_tors);
-    L->max_pairs = std::max(L->max_pairs, g.n_prec);
+    L->max_pairs = std::max(L->max_pairs, g.n_stage);
     L->max_frags = std::max(L->max_frags, H.n_frags);
     L->total_atoms += H.n_atoms;
   }
@@ -952,7 +956,7 @@ static hipError_t enqueue_phase(dock_run_s* r, bool init, int steps, hipStream_t
         a.items = r->d_items + r->lig_item_off[l];
         a.n_items = r->lig_n_items[l];
         a.queue = nullptr;
-        a.max_pairs = r->L->h_ligs[l].n_prec;
+        a.max_pairs = r->L->h_ligs[l].n_stage;
         e = timed_launch(r, a, r->lig_bucket[l], B.lpp, B.apl, r->lig_n_items[l], B.block, s);
         if (e != hipSuccess) return e;
       }
@@ -1096,7 +1100,7 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
     }
     Bucket& B = r->buckets[it->second];
     B.ligs.push_back(l);
-    B.max_pairs = std::max(B.max_pairs, L->h_ligs[l].n_prec);
+    B.max_pairs = std::max(B.max_pairs, L->h_ligs[l].n_stage);
     r->lig_bucket[l] = it->second;
   }
   std::vector<int2> items;

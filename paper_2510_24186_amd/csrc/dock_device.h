@@ -114,14 +114,13 @@ DK_INLINE float group_scan(float v) {
 // ------------------------------------------------------------------ terms
 // Pair word: i | j << 8 | type_i << 16 | type_j << 20 | flags << 24, plus the
 // radius sum as a float.  flags bit0 donor/acceptor pair, bit1 both
-// hydrophobic, bit7 empty slot (no pair).  In the pass layout the record of
-// slot s also carries, in pull, the pull list of atom s for that pass (see
-// PassPlan); it is zero otherwise.
+// hydrophobic, bit7 empty slot (no pair).  In the pass layout the n_prec
+// slot records are followed by n_prec pull words (8 bytes each, same
+// indexing): the pull list of atom s for the pass (see PassPlan).
 constexpr uint32_t kPairEmpty = 0x80u << 24;
-struct alignas(16) PairRec {
+struct PairRec {
   uint32_t w;
   float rsum;
-  uint32_t pull_lo, pull_hi;
 };
 
 // Loads through a pointer known to address global memory.  Pointers read
@@ -516,7 +515,7 @@ struct GroupSlab {
   double* fx;   // [LPP*APL]
   double* fy;
   double* fz;
-  float4* fb;   // [LPP], aliases fx/fy/fz
+  float4* fb;   // [2 LPP + 1] force entries of the pass layout, aliases fx/fy/fz
 };
 
 struct EvalOut {
@@ -763,28 +762,45 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
     // ---- pass layout: lane r evaluates slot r of every pass, stores the
     // pair force in its slot, then gathers the slots listed for its atom
     const int W = L.pass_w;
+    const uint2* pulls = reinterpret_cast<const uint2*>(pairs + L.n_prec);
+    const uint32_t none = uint32_t(2 * W) * 0x01010101u;
+    if (r == 0) S.fb[2 * W] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int ps = 0; ps < L.n_pass; ++ps) {
-      const int slot = ps * W + r;
-      const PairRec pr = pairs[r < W ? slot : ps * W];
+      const int slot = r < W ? ps * W + r : ps * W;
+      const PairRec pr = pairs[slot];
+      uint2 pw = pulls[slot];
       float f[3] = {0.f, 0.f, 0.f};
       if (r < W && !(pr.w & kPairEmpty)) {
         const int i = pr.w & 0xff, j = (pr.w >> 8) & 0xff;
         e_lane += pair_force(L, pr, S.xs[i], S.xs[j], f);
       }
-      if (r < W) S.fb[r] = make_float4(f[0], f[1], f[2], 0.f);
+      if (r < W) {
+        S.fb[r] = make_float4(f[0], f[1], f[2], 0.f);
+        S.fb[W + r] = make_float4(-f[0], -f[1], -f[2], 0.f);
+      } else {
+        pw = make_uint2(none, none);
+      }
       wave_sync();
-      uint32_t lo = r < W ? pr.pull_lo : 0u, hi = r < W ? pr.pull_hi : 0u;
-      for (int c = 0; c < L.pull_cap; ++c) {
-        const uint32_t e = lo & 0xffu;
-        lo = (lo >> 8) | (hi << 24);
-        hi >>= 8;
-        if (e & 0x80u) {
-          const float4 v = S.fb[e & 0x3fu];
-          const float sg = (e & 0x40u) ? -1.f : 1.f;
-          fsum[0][0] += sg * v.x;
-          fsum[0][1] += sg * v.y;
-          fsum[0][2] += sg * v.z;
+      // 4 or 8 entries, all read before any is summed (unused ones name the
+      // zero entry)
+      float4 v[kMaxPull];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = S.fb[(pw.x >> (8 * c)) & 0xffu];
+      if (L.pull_cap > 4) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[4 + c] = S.fb[(pw.y >> (8 * c)) & 0xffu];
+#pragma unroll
+        for (int c = 4; c < 8; ++c) {
+          fsum[0][0] += v[c].x;
+          fsum[0][1] += v[c].y;
+          fsum[0][2] += v[c].z;
         }
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        fsum[0][0] += v[c].x;
+        fsum[0][1] += v[c].y;
+        fsum[0][2] += v[c].z;
       }
       wave_sync();
     }

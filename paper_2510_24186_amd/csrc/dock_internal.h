@@ -27,8 +27,8 @@ struct alignas(16) LigDev {
   float c0[3];
   float box_min[3];
   float box_max[3];
-  int n_pass, pass_w, pull_off;           // pass layout (n_pass = 0: pairs are strided, forces by atomics)
-  int pull_cap;                           // entries per pull list
+  int n_pass, pass_w, pull_cap;           // pass layout (n_pass = 0: pairs are strided, forces by atomics)
+  int n_stage;                            // 8-byte entries to stage: pair records (+ pull words)
 };
 
 // Fragment record (DFS numbering).  Root: parent = -1, dof = -1.
@@ -116,11 +116,11 @@ void type_pair_table(int preset, TypePair table[kTypes * kTypes]);
 // `width` slots (one per lane); slot s of pass k holds pair
 // (slot_i, slot_j)[k * width + s], or -1 for an empty slot.  Every pair is in
 // exactly one slot, and no atom is an endpoint of more than `cap` slots of a
-// pass.  pulls[k * width + a] lists those slots for atom a: byte c is
-// 0x80 | slot when atom a is the pair's first endpoint (the force is added),
-// 0xC0 | slot when it is the second (subtracted), 0 past the end of the list.
-// Lanes write their slot's force to LDS with plain stores and each atom lane
-// then gathers its own entries: no LDS atomics.
+// pass.  Each pass the lane of slot s stores +f at force entry s and -f at
+// entry width + s (entry 2 * width holds zero); pulls[k * width + a] names,
+// byte by byte, the entries atom a sums: s where it is the pair's first
+// endpoint, width + s where it is the second, 2 * width past the end of its
+// list.  Plain stores and gathers: no LDS atomics.
 constexpr int kMaxPull = 8;
 struct PassPlan {
   int n_pass = 0, cap = 0;

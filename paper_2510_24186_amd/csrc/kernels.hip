@@ -111,11 +111,16 @@ DK_INLINE GroupSlab make_slab(unsigned char* base) {
   S.fb = reinterpret_cast<float4*>(S.fx);
   return S;
 }
-// coordinates (16 B per atom), then three FP64 force arrays (24 B per atom),
-// which also hold the per-slot forces of the pass layout (16 B per lane)
-constexpr size_t slab_bytes(int lpp, int apl) { return size_t(lpp) * apl * 40; }
-// pair records (16 bytes each)
-constexpr size_t pair_bytes(int max_pairs) { return size_t(max_pairs) * sizeof(PairRec); }
+// coordinates (16 B per atom), then the larger of three FP64 force arrays
+// (24 B per atom) and the force entries of the pass layout (2 * lanes + 1
+// float4)
+constexpr size_t slab_bytes(int lpp, int apl) {
+  return size_t(lpp) * apl * 16 +
+         (size_t(lpp) * apl * 24 > size_t(lpp) * 32 + 16 ? size_t(lpp) * apl * 24 : size_t(lpp) * 32 + 16);
+}
+// staged pair entries (8 bytes each), padded so the float4 slab that follows
+// is aligned
+constexpr size_t pair_bytes(int max_pairs) { return (size_t(max_pairs) * 8 + 15) / 16 * 16; }
 
 size_t score_lds_bytes(int lpp, int apl, int max_pairs) {
   const int gpb = 64 / lpp;
@@ -148,7 +153,7 @@ __global__ void __launch_bounds__(64) score_kernel(ScoreArgs a) {
   const PocketDev pk = a.pockets[lg.pocket];
   LaneLig<APL> L;
   load_lane_lig<LPP, APL>(L, lg, a.L.ligs + lig, a.L.atoms, a.L.frags, a.L.tors, pk, r);
-  for (int p = r; p < lg.n_prec; p += LPP) gp[p] = a.L.pairs[lg.pair_off + p];
+  for (int p = r; p < lg.n_stage; p += LPP) gp[p] = a.L.pairs[lg.pair_off + p];
   wave_sync();
   const float q = r < lg.n_dof ? a.q[pose * a.q_stride + r] : 0.f;
   float xo[APL][3], go[APL][3];
@@ -217,7 +222,7 @@ __global__ void __launch_bounds__(64) terms_kernel(TermsArgs a) {
   float w[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) w[k] = a.w[pi * K + k];
-  for (int p = r; p < lg.n_prec; p += LPP) gp[p] = a.L.pairs[lg.pair_off + p];
+  for (int p = r; p < lg.n_stage; p += LPP) gp[p] = a.L.pairs[lg.pair_off + p];
   wave_sync();
   float q = 0.f;
   float x[APL][3], g[APL][3], ek[K];
@@ -461,7 +466,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
     const int2 wi = a.items[item];
     const int lig = wi.x;
     const LigDev lg = a.L.ligs[lig];
-    for (int p = threadIdx.x; p < lg.n_prec; p += BLOCK) sp[p] = a.L.pairs[lg.pair_off + p];
+    for (int p = threadIdx.x; p < lg.n_stage; p += BLOCK) sp[p] = a.L.pairs[lg.pair_off + p];
     __syncthreads();
     const int traj = wi.y + grp;
     if (traj < a.n_traj) {

@@ -285,28 +285,14 @@ int prepare_ligand(int n, const uint8_t* element, const uint8_t* n_h, const floa
 
 namespace dock {
 
-PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vector<int>& pj, int width) {
-  PassPlan plan;
+namespace {
+
+// Greedy fill of passes with at most `cap` incidences per atom and pass.
+void fill_passes(int n_atoms, const std::vector<int>& pi, const std::vector<int>& pj, int width, int cap,
+                 const std::vector<int>& order, PassPlan& plan) {
   const size_t P = pi.size();
-  if (P == 0) return plan;
-  std::vector<int> deg(n_atoms, 0);
-  for (size_t p = 0; p < P; ++p) {
-    ++deg[pi[p]];
-    ++deg[pj[p]];
-  }
-  const int max_deg = *std::max_element(deg.begin(), deg.end());
-  const int passes0 = int((P + width - 1) / width);
-  // incidences one atom may take per pass: enough for a full pass on
-  // average (2 * width / n_atoms) and for the busiest atom to finish within
-  // the minimal pass count, plus one of slack; at most kMaxPull
-  int cap = std::max((2 * width + n_atoms - 1) / n_atoms, (max_deg + passes0 - 1) / passes0) + 1;
-  cap = std::min(cap, kMaxPull);
-  // pairs touching busy atoms first, so that hubs spread over every pass
-  std::vector<int> order(P);
-  for (size_t p = 0; p < P; ++p) order[p] = int(p);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return std::max(deg[pi[a]], deg[pj[a]]) > std::max(deg[pi[b]], deg[pj[b]]);
-  });
+  plan = PassPlan();
+  plan.cap = cap;
   std::vector<char> used(P, 0);
   std::vector<int> cnt(n_atoms);
   size_t placed = 0, first_free = 0;
@@ -332,9 +318,46 @@ PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vec
     }
     ++plan.n_pass;
   }
-  plan.cap = cap;
-  // pull lists: per pass and atom, the slots that hold its pairs
-  plan.pulls.assign(size_t(plan.n_pass) * width, 0ull);
+}
+
+}  // namespace
+
+PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vector<int>& pj, int width) {
+  PassPlan plan;
+  const size_t P = pi.size();
+  if (P == 0) return plan;
+  std::vector<int> deg(n_atoms, 0);
+  for (size_t p = 0; p < P; ++p) {
+    ++deg[pi[p]];
+    ++deg[pj[p]];
+  }
+  const int max_deg = *std::max_element(deg.begin(), deg.end());
+  const int passes0 = int((P + width - 1) / width);
+  // pairs touching busy atoms first, so that hubs spread over every pass
+  std::vector<int> order(P);
+  for (size_t p = 0; p < P; ++p) order[p] = int(p);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return std::max(deg[pi[a]], deg[pj[a]]) > std::max(deg[pi[b]], deg[pj[b]]);
+  });
+  // incidences one atom may take per pass: enough for a full pass on
+  // average (2 * width / n_atoms) and for the busiest atom to finish within
+  // the minimal pass count, plus one of slack.  The gather reads 4 or 8
+  // entries per pass, so a cap of 4 is also tried and the cheaper plan kept
+  // (cost ~ passes * (pair work + gather work)).
+  int cap = std::max((2 * width + n_atoms - 1) / n_atoms, (max_deg + passes0 - 1) / passes0) + 1;
+  cap = std::min(cap, kMaxPull);
+  fill_passes(n_atoms, pi, pj, width, cap, order, plan);
+  if (cap > 4) {
+    PassPlan p4;
+    fill_passes(n_atoms, pi, pj, width, 4, order, p4);
+    const auto cost = [](const PassPlan& q) { return double(q.n_pass) * (100.0 + 5.0 * (q.cap <= 4 ? 4 : 8)); };
+    if (cost(p4) <= cost(plan)) plan = std::move(p4);
+  }
+  // pull lists: per pass and atom, the force entries of its pairs (slot s
+  // for the first endpoint, width + s for the second); unused bytes name the
+  // zero entry 2 * width
+  const uint64_t none = uint64_t(2 * width) * 0x0101010101010101ull;
+  plan.pulls.assign(size_t(plan.n_pass) * width, none);
   std::vector<int> k_of(n_atoms);
   for (int ps = 0; ps < plan.n_pass; ++ps) {
     std::fill(k_of.begin(), k_of.end(), 0);
@@ -343,8 +366,9 @@ PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vec
       if (a < 0) continue;
       uint64_t& la = plan.pulls[size_t(ps) * width + a];
       uint64_t& lb = plan.pulls[size_t(ps) * width + b];
-      la |= uint64_t(0x80u | unsigned(s)) << (8 * k_of[a]++);
-      lb |= uint64_t(0xC0u | unsigned(s)) << (8 * k_of[b]++);
+      const int ka = 8 * k_of[a]++, kb = 8 * k_of[b]++;
+      la = (la & ~(0xffull << ka)) | (uint64_t(s) << ka);
+      lb = (lb & ~(0xffull << kb)) | (uint64_t(width + s) << kb);
     }
   }
   return plan;
