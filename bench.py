@@ -29,14 +29,40 @@ sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
 
-PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+# FP32 vector peak this build can reach: 256 CUs x 4 SIMDs x 16 lanes x 2
+# flops (FMA) x 2.4 GHz.  MI355X's published 157.3 TFLOP/s counts packed FP32,
+# which the build disables.
+PEAK_FP32_TFLOPS = 78.6
+PEAK_FP32_PACKED_TFLOPS = 157.3
 N_LOCAL = 10
 
 
 def flops_per_eval(n_atoms, n_pairs, n_tors):
     """Algorithmic FP32 operations of one score+gradient evaluation plus its
-    Adam update (counted from the method's arithmetic)."""
+    Adam update, counted from the method's arithmetic: per atom 120 (placement
+    18, trilinear value and gradient 84, torque terms 18), per intra pair 30,
+    per torsion 124 (Rodrigues matrix, composition, gradient, Adam), per pose
+    150 (rotation, rigid gradient, energy reduction, six Adam updates)."""
     return 120.0 * n_atoms + 30.0 * n_pairs + 124.0 * n_tors + 150.0
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per MC-step launch of one sampler bucket from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs (calibrated on a copy kernel), or
+    None when the kernel sources changed since those runs."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2510_24186_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    launch = rec["launches"].get(kernel_key)
+    return None if launch is None else float(launch["bytes"])
 
 
 def ligand_table(D, H):
@@ -199,8 +225,11 @@ def main():
     tot_ms = sum(np.mean(d["ms"]) for d in per_bucket.values())
     dom = max(per_bucket.values(), key=lambda d: np.mean(d["ms"]))
     achieved = dom["flop"] / (np.mean(dom["ms"]) * 1e-3) / 1e12
+    traffic = measured_traffic("%d,%d,%d,false" % (dom["lanes"], dom["apl"], dom["block"]))
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_FP32_TFLOPS, 4), traffic=None,
+                    frac=round(achieved / PEAK_FP32_TFLOPS, 4),
+                    traffic=None if traffic is None else round(traffic),
+                    frac_of_packed_peak=round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
                     kernel="sample_kernel<%d,%d,%d>" % (dom["lanes"], dom["apl"], dom["block"]),
                     launch_ms=round(float(np.mean(dom["ms"])), 3),
                     all_launches_tflops=round(tot_flop / (tot_ms * 1e-3) / 1e12, 3),
