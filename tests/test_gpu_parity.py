@@ -70,6 +70,22 @@ def test_maps_full_tiny_grid(D, preset):
     assert np.all(np.abs(Gt - ref) <= ulp + 1e-12)
 
 
+@pytest.mark.parametrize("preset", [P.PRESET_TRIDS, P.PRESET_VINA])
+def test_maps_full_600_atom_pocket(D, preset):
+    # every node of the 40^3 x 8 maps: the FP32 cutoff decision must match the
+    # oracle's bit for bit (a fused multiply-add in d^2 flips a few nodes)
+    pk = synth.workload("C1", n_lig=1)[0][0]
+    G.say("maps full 600-atom pocket preset", preset, pk.dims)
+    w = G.weights32(preset)
+    p = G.load_pocket(pk, preset, w, keep=True)
+    M = D.dock_pocket_maps(p).cpu().numpy().reshape(8, -1)
+    Gt = D.dock_pocket_maps(p, per_term=True).cpu().numpy().reshape(8, P.n_terms(preset), -1)
+    ref = MAPS.build_maps(pk, preset).reshape(8, P.n_terms(preset), -1)
+    _map_check(M, ref, w, "C1 full")
+    ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(Gt - ref) <= ulp + 1e-12)
+
+
 @pytest.mark.parametrize("name,preset", [("C1", P.PRESET_TRIDS), ("C2", P.PRESET_TRIDS),
                                          ("C2", P.PRESET_VINA)])
 def test_maps_sampled_nodes(D, name, preset):
