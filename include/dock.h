@@ -312,6 +312,17 @@ int dock_best_poses(dock_ligands_t L, int32_t n_traj, const float* E_best, const
                     float* E_out, float* E_screen, float* q_out, int32_t* idx_out,
                     float* xyz_out, int32_t xyz_stride, int32_t* n_out, void* stream);
 
+/* Screening rank across ligands (Methods, E_screen: virtual screening
+ * ranks compounds by it).  scores: device, one score per ligand at
+ * scores[i * stride] (for instance a ligand's best E_screen, column 0 of
+ * dock_best_poses' E_screen with stride = top_n), n ligands.  Writes the
+ * top_k lowest (1 <= top_k <= 1024) to score_out / lig_out (device
+ * [top_k]) in ascending order; equal scores rank by lower ligand index,
+ * -0.0 equals +0.0, NaN ranks after +inf; slots beyond n get +inf and -1.
+ * Allocates its scratch on the stream (stream-ordered) and returns at once. */
+int dock_screen_rank(const float* scores, int64_t n, int32_t stride, int32_t top_k, float* score_out,
+                     int32_t* lig_out, void* stream);
+
 /* Raw Philox4x32-10 blocks from the sampler's generator (Salmon et al.,
  * SC'11): out[4i..4i+3] = Philox(counter = counters[4i..4i+3], key = (k0, k1)).
  * counters, out: device [n * 4] uint32.  For checking the random stream. */

@@ -50,3 +50,22 @@ def best_poses(topo, E_best, q_best, top_n=8, rmsd_cut=1.0, w_tor=0.01, margins=
     if margins:
         out["rmsd_margin"] = margin
     return out
+
+
+def screen_rank(scores, top_k):
+    """Cross-ligand screening rank (Methods, E_screen): the top_k lowest
+    scores in ascending order, equal scores by lower ligand index, NaN after
+    +inf, -0.0 equal to +0.0; slots beyond the number of ligands get +inf and
+    -1.  Returns (scores [top_k], ligand indices [top_k])."""
+    v = np.asarray(scores, np.float64)
+    n = len(v)
+    # primary key: the score with NaN ordered last; secondary: the index
+    nan = np.isnan(v)
+    key = np.where(nan, 0.0, v)
+    order = np.lexsort((np.arange(n), key, nan))
+    k = min(top_k, n)
+    out_s = np.full(top_k, np.inf)
+    out_i = np.full(top_k, -1, np.int64)
+    out_s[:k] = v[order[:k]]
+    out_i[:k] = order[:k]
+    return out_s, out_i

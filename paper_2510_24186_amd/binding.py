@@ -98,6 +98,7 @@ _sig("dock_run_set_state", C.c_int, _p, _p, _p, _p, _p, _i32, _p)
 _sig("dock_run_kernel_ms", C.c_int, _p, C.POINTER(_f32))
 _sig("dock_free_run", C.c_int, _p)
 _sig("dock_philox", C.c_int, _p, C.c_uint32, C.c_uint32, C.c_int64, _p, _p)
+_sig("dock_screen_rank", C.c_int, _p, C.c_int64, _i32, _i32, _p, _p, _p)
 _sig("dock_best_poses", C.c_int, _p, _i32, _p, _p, _i32, _i32, _f32, _f32, _p, _p, _p, _p, _p, _i32,
      _p, _p)
 
@@ -515,6 +516,19 @@ def dock_philox(counters, k0, k1, stream=None):
     _check(lib.dock_philox(_dptr(c), int(k0) & 0xFFFFFFFF, int(k1) & 0xFFFFFFFF, c.shape[0],
                            _dptr(out), _stream(stream)))
     return out
+
+
+def dock_screen_rank(scores, top_k, stride=1, stream=None):
+    """scores: float32 CUDA tensor holding one score per ligand every `stride`
+    elements -> (score [top_k], ligand index [top_k]), ascending."""
+    import torch
+    s = _cuda_check(scores.contiguous(), torch.float32, "scores")
+    n = (s.numel() + stride - 1) // stride
+    out_s = torch.empty(int(top_k), dtype=torch.float32, device=s.device)
+    out_i = torch.empty(int(top_k), dtype=torch.int32, device=s.device)
+    _check(lib.dock_screen_rank(_dptr(s), n, int(stride), int(top_k), _dptr(out_s), _dptr(out_i),
+                                _stream(stream)))
+    return out_s, out_i
 
 
 def dock_abi_version():

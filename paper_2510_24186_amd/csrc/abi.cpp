@@ -1426,6 +1426,59 @@ int dock_best_poses(dock_ligands_t L, int32_t n_traj, const float* E_best, const
   return DOCK_OK;
 }
 
+int dock_screen_rank(const float* scores, int64_t n, int32_t stride, int32_t top_k, float* score_out,
+                     int32_t* lig_out, void* stream) {
+  if (n < 0 || n > (int64_t(1) << 31) - 2) return fail(DOCK_E_ARG, "n must be in [0, 2^31 - 2]");
+  if (stride < 1) return fail(DOCK_E_ARG, "stride must be >= 1");
+  if (top_k < 1 || top_k > 1024) return fail(DOCK_E_ARG, "top_k must be in [1, 1024]");
+  if (!score_out || !lig_out || (n > 0 && !scores)) return fail(DOCK_E_ARG, "null array");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // each pass keeps top_k of every block of kRankBlock entries (at least
+  // halving the count) until one block remains; its output is the answer
+  RankArgs a{};
+  a.score = scores;
+  a.idx = nullptr;
+  a.n = n;
+  a.stride = stride;
+  a.k = top_k;
+  const long long blocks0 = (n + kRankBlock - 1) / kRankBlock;
+  float* bufs[2] = {nullptr, nullptr};
+  int* ibufs[2] = {nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  if (blocks0 > 1) {
+    const size_t cap = size_t(blocks0) * size_t(top_k);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+      e = hipMallocAsync(reinterpret_cast<void**>(&bufs[b]), cap * sizeof(float), s);
+      if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&ibufs[b]), cap * sizeof(int), s);
+    }
+  }
+  int cur = 0;
+  while (e == hipSuccess) {
+    const long long blocks = (a.n + kRankBlock - 1) / kRankBlock;
+    if (blocks <= 1) {
+      // final pass, straight into the outputs (n = 0: one block of empty slots)
+      a.out_score = score_out;
+      a.out_idx = lig_out;
+      e = launch_rank(a, s);
+      break;
+    }
+    a.out_score = bufs[cur];
+    a.out_idx = ibufs[cur];
+    e = launch_rank(a, s);
+    a.score = bufs[cur];
+    a.idx = ibufs[cur];
+    a.n = blocks * top_k;
+    a.stride = 1;
+    cur ^= 1;
+  }
+  for (int b = 0; b < 2; ++b) {
+    if (bufs[b]) (void)hipFreeAsync(bufs[b], s);
+    if (ibufs[b]) (void)hipFreeAsync(ibufs[b], s);
+  }
+  if (e != hipSuccess) return fail(DOCK_E_HIP, hipGetErrorString(e));
+  return DOCK_OK;
+}
+
 int dock_philox(const uint32_t* counters, uint32_t k0, uint32_t k1, int64_t n, uint32_t* out,
                 void* stream) {
   if (n < 0) return fail(DOCK_E_ARG, "negative n");

@@ -114,6 +114,20 @@ hipError_t launch_score(const ScoreArgs& a, int lpp, int apl, bool direct, hipSt
 hipError_t launch_sample(const SampleArgs& a, int lpp, int apl, int grid, int block, bool direct,
                          hipStream_t s);
 hipError_t launch_best(const BestArgs& a, hipStream_t s);
+
+// Screening rank: one pass reduces every block of kRankBlock (score, index)
+// entries to its k smallest.
+constexpr int kRankBlock = 2048;
+struct RankArgs {
+  const float* score;  // first pass: strided ligand scores; later: packed
+  const int* idx;      // null on the first pass (index = position)
+  long long n;
+  int stride;
+  int k;
+  float* out_score;
+  int* out_idx;
+};
+hipError_t launch_rank(const RankArgs& a, hipStream_t s);
 hipError_t launch_terms(const TermsArgs& a, int lpp, int apl, int K, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, long long n, uint32_t* out,
                          hipStream_t s);

@@ -9,6 +9,8 @@
 //                 persistent (device work queue over ragged-packed items)
 //  best_kernel    per ligand: bitonic sort of the trajectories' best
 //                 energies, greedy RMSD clustering, top N
+//  rank_kernel    screening rank across ligands: blocks of 2,048 scores
+//                 sorted in LDS and cut to the k smallest, pass by pass
 #include <float.h>
 #include <math.h>
 
@@ -620,6 +622,72 @@ hipError_t launch_best(const BestArgs& a, hipStream_t s) {
   const size_t lds = (size_t(a.t_pad) * 8 + 15) / 16 * 16 + size_t(a.top_n) * kMaxAtoms * 16;
   if (a.n_ligands <= 0) return hipSuccess;
   hipLaunchKernelGGL(best_kernel, dim3(a.n_ligands), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+// ================================================================ screening rank
+
+// Total order on (score, index): the score's bits mapped to an unsigned key
+// that sorts like the float (-0.0 as +0.0, every NaN after +inf), the
+// ligand index breaking ties.
+DK_INLINE unsigned long long rank_key(float v, int idx) {
+  uint32_t u = __float_as_uint(v);
+  if (v != v) u = 0xffffffffu;
+  else if (u == 0x80000000u) u = 0u;
+  if (u != 0xffffffffu) u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return (static_cast<unsigned long long>(u) << 32) | static_cast<uint32_t>(idx);
+}
+
+__global__ void __launch_bounds__(256) rank_kernel(RankArgs a) {
+  __shared__ unsigned long long key[kRankBlock];
+  __shared__ float val[kRankBlock];
+  const long long base = (long long)blockIdx.x * kRankBlock;
+  for (int t = threadIdx.x; t < kRankBlock; t += 256) {
+    const long long e = base + t;
+    if (e < a.n) {
+      const float v = a.idx ? a.score[e] : a.score[e * a.stride];
+      const int id = a.idx ? a.idx[e] : int(e);
+      // an empty slot of an earlier pass (index -1) stays empty
+      key[t] = id < 0 ? ~0ull : rank_key(v, id);
+      val[t] = v;
+    } else {
+      key[t] = ~0ull;
+      val[t] = __int_as_float(0x7f800000);
+    }
+  }
+  __syncthreads();
+  // bitonic sort of kRankBlock keys (values follow their key)
+  for (int size = 2; size <= kRankBlock; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < kRankBlock / 2; t += 256) {
+        const int lo = 2 * t - (t & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const unsigned long long kl = key[lo], kh = key[hi];
+        if ((kl > kh) == up) {
+          key[lo] = kh;
+          key[hi] = kl;
+          const float vl = val[lo];
+          val[lo] = val[hi];
+          val[hi] = vl;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int keep = a.k < kRankBlock ? a.k : kRankBlock;
+  for (int t = threadIdx.x; t < keep; t += 256) {
+    const unsigned long long kv = key[t];
+    const bool none = kv == ~0ull;
+    a.out_score[(long long)blockIdx.x * keep + t] = none ? __int_as_float(0x7f800000) : val[t];
+    a.out_idx[(long long)blockIdx.x * keep + t] = none ? -1 : int(uint32_t(kv));
+  }
+}
+
+hipError_t launch_rank(const RankArgs& a, hipStream_t s) {
+  const long long nb = (a.n + kRankBlock - 1) / kRankBlock;
+  const unsigned blocks = unsigned(nb > 0 ? nb : 1);
+  hipLaunchKernelGGL(rank_kernel, dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -303,3 +303,21 @@ def test_optimizer_variants_update_rules(D, opt):
                 d[:3] = np.abs(got[:3] - nxt[:3])
                 tol = 2e-4 * (1 + np.abs(step).max()) if opt == "SGD" else 2e-4
                 assert d.max() < tol, (opt, t, s, k, d.max())
+
+
+@pytest.mark.parametrize("n,k,stride", [(0, 5, 1), (1, 1, 1), (100, 37, 3), (2048, 1024, 1),
+                                        (2049, 1024, 2), (70000, 300, 1)])
+def test_screen_rank_matches_oracle(D, n, k, stride):
+    G.say("screen rank n", n, "k", k, "stride", stride)
+    rng = np.random.default_rng(n + k)
+    v = rng.normal(size=n * stride).astype(np.float32)
+    # ties, signed zeros, infinities and NaNs
+    special = rng.choice(np.array([-1.0, -0.0, 0.0, np.inf, -np.inf, np.nan], np.float32), size=v.shape)
+    v = np.where(rng.random(v.shape) < 0.2, special, v).astype(np.float32)
+    if n > 0:
+        v[::7] = np.float32(0.25)
+    s, idx = D.dock_screen_rank(torch.tensor(v, device="cuda"), k, stride=stride)
+    torch.cuda.synchronize()
+    rs, ridx = BEST.screen_rank(v[::stride][:n].astype(np.float64), k)
+    assert np.array_equal(idx.cpu().numpy(), ridx.astype(np.int32))
+    np.testing.assert_array_equal(s.cpu().numpy(), rs.astype(np.float32))

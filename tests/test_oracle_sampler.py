@@ -304,3 +304,33 @@ def test_optimizer_variants_match_torch_fp64(kind):
         loss.backward()
         opt.step()
     np.testing.assert_allclose(q[0], t.detach().numpy(), rtol=1e-12, atol=1e-13)
+
+
+# ---------------------------------------------------------------- screening rank
+
+def _rank_brute(v, k):
+    # a plain sort with an explicit key, independent of screen_rank's lexsort
+    items = sorted(range(len(v)), key=lambda i: (math.isnan(v[i]), 0.0 if math.isnan(v[i]) else v[i], i))
+    s = [v[i] for i in items[:k]] + [math.inf] * max(0, k - len(v))
+    idx = items[:k] + [-1] * max(0, k - len(v))
+    return s, idx
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_screen_rank_against_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(0, 40))
+    v = rng.choice([-3.0, -1.5, -0.0, 0.0, 2.0, np.inf, np.nan, -np.inf], size=n)
+    v = np.where(rng.random(n) < 0.5, rng.normal(size=n), v)
+    for k in (1, 5, 50):
+        s, idx = BEST.screen_rank(v, k)
+        bs, bidx = _rank_brute(list(v), k)
+        assert list(idx) == bidx
+        np.testing.assert_array_equal(np.asarray(s), np.asarray(bs))
+
+
+def test_screen_rank_ties_and_specials():
+    v = [1.0, -0.0, 0.0, np.nan, -2.0, 1.0, np.inf, -2.0]
+    s, idx = BEST.screen_rank(v, 10)
+    assert list(idx) == [4, 7, 1, 2, 0, 5, 6, 3, -1, -1]
+    assert np.isinf(s[-1]) and np.isnan(s[7])
