@@ -529,8 +529,10 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
       g.n_pass = plan.n_pass;
       g.pass_w = lc.lpp;
       g.pull_cap = plan.cap;
-      for (size_t s = 0; s < plan.slot_i.size(); ++s) pairs.push_back(record(plan.slot_i[s], plan.slot_j[s]));
-      for (size_t s = 0; s < plan.pulls.size(); ++s) {
+      // slot record and the pull word of atom `slot` side by side: one
+      // 16-byte load per lane and pass
+      for (size_t s = 0; s < plan.slot_i.size(); ++s) {
+        pairs.push_back(record(plan.slot_i[s], plan.slot_j[s]));
         PairRec pw;
         pw.w = uint32_t(plan.pulls[s]);
         const uint32_t hi = uint32_t(plan.pulls[s] >> 32);

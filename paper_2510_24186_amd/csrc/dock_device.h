@@ -66,6 +66,13 @@ template <int W>
 DK_INLINE float shfl(float v, int src) { return bp(bp_addr<W>(src), v); }
 template <int W>
 DK_INLINE int shfl(int v, int src) { return bp(bp_addr<W>(src), v); }
+// Value of lane `src` (the same for every lane of the group) to all lanes of
+// the group: a scalar read of one lane when the group is the whole wave.
+template <int W>
+DK_INLINE float bcast(float v, int src) {
+  if (W == 64) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+  return shfl<W>(v, src);
+}
 
 // DPP controls (GFX9 encoding)
 constexpr int kDppQuadXor1 = 0xB1;    // quad_perm [1,0,3,2]
@@ -114,9 +121,9 @@ DK_INLINE float group_scan(float v) {
 // ------------------------------------------------------------------ terms
 // Pair word: i | j << 8 | type_i << 16 | type_j << 20 | flags << 24, plus the
 // radius sum as a float.  flags bit0 donor/acceptor pair, bit1 both
-// hydrophobic, bit7 empty slot (no pair).  In the pass layout the n_prec
-// slot records are followed by n_prec pull words (8 bytes each, same
-// indexing): the pull list of atom s for the pass (see PassPlan).
+// hydrophobic, bit7 empty slot (no pair).  In the pass layout each slot
+// record is followed by an 8-byte pull word (the pull list of atom `slot` for
+// the pass, see PassPlan), so record p sits at entry 2p.
 constexpr uint32_t kPairEmpty = 0x80u << 24;
 struct PairRec {
   uint32_t w;
@@ -531,16 +538,20 @@ struct Rigid {
 // Forward kinematics: world coordinates of the atoms owned by lane r.
 // Fragment transforms are composed root-to-leaf by pointer jumping
 // (ceil(log2) rounds of "compose with my current ancestor's transform").
+// With T4 (LDS, 3 * LPP float4 of the group) the transforms are exchanged as
+// three float4 rows per fragment (3 stores + 3 loads per round, 3 loads per
+// atom) instead of one shuffle per element; without it, by shuffles only.
 template <int LPP, int APL>
-DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][3]) {
+DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][3],
+                         float4* T4 = nullptr) {
   // ---- each lane takes sin/cos of its own angle DOF once; the rigid part
   // and every fragment's torsion are then fetched from the owning lanes
   float sq, cq;
   sincosf(r >= 3 ? q : 0.f, &sq, &cq);
-  const float Tx = shfl<LPP>(q, 0), Ty = shfl<LPP>(q, 1), Tz = shfl<LPP>(q, 2);
-  const float sa = shfl<LPP>(sq, 3), ca = shfl<LPP>(cq, 3);
-  const float sb = shfl<LPP>(sq, 4), cb = shfl<LPP>(cq, 4);
-  const float sg = shfl<LPP>(sq, 5), cg = shfl<LPP>(cq, 5);
+  const float Tx = bcast<LPP>(q, 0), Ty = bcast<LPP>(q, 1), Tz = bcast<LPP>(q, 2);
+  const float sa = bcast<LPP>(sq, 3), ca = bcast<LPP>(cq, 3);
+  const float sb = bcast<LPP>(sq, 4), cb = bcast<LPP>(cq, 4);
+  const float sg = bcast<LPP>(sq, 5), cg = bcast<LPP>(cq, 5);
   // ---- fragment transforms: lane f starts from its own local transform
   const int tsrc = bp_addr<LPP>(L.fdof >= 0 ? L.fdof : 0);
   const float st = bp(tsrc, sq), ct = bp(tsrc, cq);
@@ -566,41 +577,76 @@ DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][
     t[2] = L.fxb[2] - (m[6] * L.fxb[0] + m[7] * L.fxb[1] + m[8] * L.fxb[2]);
   }
   // pointer jumping: C_f <- C_anc o C_f until every fragment reaches the root
-  for (int it = 0; it < L.fk_rounds; ++it) {
-    const int ad = bp_addr<LPP>(anc >= 0 ? anc : r);
-    float a[9], b[3];
+  auto compose = [&](const float (&a)[9], const float (&b)[3]) {
+    float nm[9], nt[3];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) a[k] = bp(ad, m[k]);
+    for (int i = 0; i < 3; ++i) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) b[k] = bp(ad, t[k]);
-    const int anc2 = bp(ad, anc);
-    if (anc >= 0) {
-      float nm[9], nt[3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-          nm[3 * i + j] = a[3 * i] * m[j] + a[3 * i + 1] * m[3 + j] + a[3 * i + 2] * m[6 + j];
-        nt[i] = a[3 * i] * t[0] + a[3 * i + 1] * t[1] + a[3 * i + 2] * t[2] + b[i];
-      }
-#pragma unroll
-      for (int k = 0; k < 9; ++k) m[k] = nm[k];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) t[k] = nt[k];
-      anc = anc2;
+      for (int j = 0; j < 3; ++j)
+        nm[3 * i + j] = a[3 * i] * m[j] + a[3 * i + 1] * m[3 + j] + a[3 * i + 2] * m[6 + j];
+      nt[i] = a[3 * i] * t[0] + a[3 * i + 1] * t[1] + a[3 * i + 2] * t[2] + b[i];
     }
-  }
 #pragma unroll
-  for (int s = 0; s < APL; ++s) {
-    const int ad = bp_addr<LPP>(L.afrag[s]);
-    float a[9], b[3];
+    for (int k = 0; k < 9; ++k) m[k] = nm[k];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) a[k] = bp(ad, m[k]);
+    for (int k = 0; k < 3; ++k) t[k] = nt[k];
+  };
+  if (T4) {
+    for (int it = 0; it < L.fk_rounds; ++it) {
+      T4[r] = make_float4(m[0], m[1], m[2], t[0]);
+      T4[LPP + r] = make_float4(m[3], m[4], m[5], t[1]);
+      T4[2 * LPP + r] = make_float4(m[6], m[7], m[8], t[2]);
+      wave_sync();
+      const int src = anc >= 0 ? anc : r;
+      const int anc2 = bp(bp_addr<LPP>(src), anc);
+      const float4 r0 = T4[src], r1 = T4[LPP + src], r2 = T4[2 * LPP + src];
+      wave_sync();
+      if (anc >= 0) {
+        const float a[9] = {r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, r2.x, r2.y, r2.z};
+        const float b[3] = {r0.w, r1.w, r2.w};
+        compose(a, b);
+        anc = anc2;
+      }
+    }
+    T4[r] = make_float4(m[0], m[1], m[2], t[0]);
+    T4[LPP + r] = make_float4(m[3], m[4], m[5], t[1]);
+    T4[2 * LPP + r] = make_float4(m[6], m[7], m[8], t[2]);
+    wave_sync();
 #pragma unroll
-    for (int k = 0; k < 3; ++k) b[k] = bp(ad, t[k]);
-    x[s][0] = a[0] * L.ax[s] + a[1] * L.ay[s] + a[2] * L.az[s] + b[0];
-    x[s][1] = a[3] * L.ax[s] + a[4] * L.ay[s] + a[5] * L.az[s] + b[1];
-    x[s][2] = a[6] * L.ax[s] + a[7] * L.ay[s] + a[8] * L.az[s] + b[2];
+    for (int s = 0; s < APL; ++s) {
+      const int f = L.afrag[s];
+      const float4 r0 = T4[f], r1 = T4[LPP + f], r2 = T4[2 * LPP + f];
+      x[s][0] = r0.x * L.ax[s] + r0.y * L.ay[s] + r0.z * L.az[s] + r0.w;
+      x[s][1] = r1.x * L.ax[s] + r1.y * L.ay[s] + r1.z * L.az[s] + r1.w;
+      x[s][2] = r2.x * L.ax[s] + r2.y * L.ay[s] + r2.z * L.az[s] + r2.w;
+    }
+    wave_sync();  // the rows are overwritten by the caller's coordinate slab
+  } else {
+    for (int it = 0; it < L.fk_rounds; ++it) {
+      const int ad = bp_addr<LPP>(anc >= 0 ? anc : r);
+      float a[9], b[3];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) a[k] = bp(ad, m[k]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) b[k] = bp(ad, t[k]);
+      const int anc2 = bp(ad, anc);
+      if (anc >= 0) {
+        compose(a, b);
+        anc = anc2;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < APL; ++s) {
+      const int ad = bp_addr<LPP>(L.afrag[s]);
+      float a[9], b[3];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) a[k] = bp(ad, m[k]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) b[k] = bp(ad, t[k]);
+      x[s][0] = a[0] * L.ax[s] + a[1] * L.ay[s] + a[2] * L.az[s] + b[0];
+      x[s][1] = a[3] * L.ax[s] + a[4] * L.ay[s] + a[5] * L.az[s] + b[1];
+      x[s][2] = a[6] * L.ax[s] + a[7] * L.ay[s] + a[8] * L.az[s] + b[2];
+    }
   }
   Rigid rg;
   rg.Tx = Tx; rg.Ty = Ty; rg.Tz = Tz;
@@ -730,7 +776,7 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
   launder(L);
   // ---- atoms: place, interpolate, publish coordinates to the slab
   float x[APL][3], g[APL][3];
-  const Rigid rg = fk_place<LPP, APL>(L, q, r, x);
+  const Rigid rg = fk_place<LPP, APL>(L, q, r, x, S.xs);
   float e_lane = 0.f;
 #pragma unroll
   for (int s = 0; s < APL; ++s) {
@@ -762,13 +808,16 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
     // ---- pass layout: lane r evaluates slot r of every pass, stores the
     // pair force in its slot, then gathers the slots listed for its atom
     const int W = L.pass_w;
-    const uint2* pulls = reinterpret_cast<const uint2*>(pairs + L.n_prec);
+    const uint4* recs = reinterpret_cast<const uint4*>(pairs);
     const uint32_t none = uint32_t(2 * W) * 0x01010101u;
     if (r == 0) S.fb[2 * W] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int ps = 0; ps < L.n_pass; ++ps) {
       const int slot = r < W ? ps * W + r : ps * W;
-      const PairRec pr = pairs[slot];
-      uint2 pw = pulls[slot];
+      const uint4 rp = recs[slot];
+      PairRec pr;
+      pr.w = rp.x;
+      pr.rsum = __uint_as_float(rp.y);
+      uint2 pw = make_uint2(rp.z, rp.w);
       float f[3] = {0.f, 0.f, 0.f};
       if (r < W && !(pr.w & kPairEmpty)) {
         const int i = pr.w & 0xff, j = (pr.w >> 8) & 0xff;
@@ -873,7 +922,7 @@ DK_INLINE float eval_terms(const LaneLig<APL>& L, float q, float (&x)[APL][3], f
                            Rigid& rg, const float* __restrict__ G, const GridDev& grid,
                            const float (&w)[K], const PairRec* __restrict__ pairs, const GroupSlab& S,
                            int r, float dLdE, float* __restrict__ dLdG, float (&ek)[K]) {
-  if (!XIN) rg = fk_place<LPP, APL>(L, q, r, x);
+  if (!XIN) rg = fk_place<LPP, APL>(L, q, r, x, S.xs);
   const size_t nxyz = size_t(grid.dims[0]) * grid.dims[1] * grid.dims[2];
   const int nx = grid.dims[0], nxy = grid.dims[0] * grid.dims[1];
   float el[K];
@@ -926,8 +975,9 @@ DK_INLINE float eval_terms(const LaneLig<APL>& L, float q, float (&x)[APL][3], f
     }
   }
   wave_sync();
+  const int pstep = L.n_pass > 0 ? 2 : 1;
   for (int p = r; p < L.n_prec; p += LPP) {
-    const PairRec pr = pairs[p];
+    const PairRec pr = pairs[pstep * p];
     if (pr.w & kPairEmpty) continue;
     const int i = pr.w & 0xff, j = (pr.w >> 8) & 0xff;
     const float4 xi = S.xs[i], xj = S.xs[j];
