@@ -312,6 +312,21 @@ int dock_best_poses(dock_ligands_t L, int32_t n_traj, const float* E_best, const
                     float* E_out, float* E_screen, float* q_out, int32_t* idx_out,
                     float* xyz_out, int32_t xyz_stride, int32_t* n_out, void* stream);
 
+/* Adjoint of the grid-map build for the TRIDS terms (Methods, E_long,
+ * E_clash, E_Hbond): with lam = dL/dG for the per-term maps (device float
+ * [8][3][nz][ny][nx], the layout dock_pocket_copy_maps returns per term),
+ * accumulates (+=)
+ *   dLdxyz   [n_atoms * 3] device float, caller atom order: dL/d receptor xyz
+ *   dLdtheta [DOCK_MAP_THETA] device double: dL/d(mu_long, sigma_long, mu_hb,
+ *            sigma_hb, d_clash_hb, R_0 .. R_7) at the library's constants
+ *            (3, sqrt 2, 2.88, 0.3, 2.6, the type radii)
+ * (either may be null).  Cutoff decisions are the map build's; the fixed
+ * cutoffs (10 A, 3.4 A) are not differentiated.  Grid-mode TRIDS pockets
+ * only (DOCK_E_ARG otherwise).  Asynchronous on the stream. */
+#define DOCK_MAP_THETA 13
+int dock_pocket_map_adjoint(dock_pocket_t p, const float* dLdG, float* dLdxyz, double* dLdtheta,
+                            void* stream);
+
 /* Screening rank across ligands (Methods, E_screen: virtual screening
  * ranks compounds by it).  scores: device, one score per ligand at
  * scores[i * stride] (for instance a ligand's best E_screen, column 0 of

@@ -99,6 +99,7 @@ _sig("dock_run_kernel_ms", C.c_int, _p, C.POINTER(_f32))
 _sig("dock_free_run", C.c_int, _p)
 _sig("dock_philox", C.c_int, _p, C.c_uint32, C.c_uint32, C.c_int64, _p, _p)
 _sig("dock_screen_rank", C.c_int, _p, C.c_int64, _i32, _i32, _p, _p, _p)
+_sig("dock_pocket_map_adjoint", C.c_int, _p, _p, _p, _p, _p)
 _sig("dock_best_poses", C.c_int, _p, _i32, _p, _p, _i32, _i32, _f32, _f32, _p, _p, _p, _p, _p, _i32,
      _p, _p)
 
@@ -529,6 +530,19 @@ def dock_screen_rank(scores, top_k, stride=1, stream=None):
     _check(lib.dock_screen_rank(_dptr(s), n, int(stride), int(top_k), _dptr(out_s), _dptr(out_i),
                                 _stream(stream)))
     return out_s, out_i
+
+
+def dock_pocket_map_adjoint(pocket, dLdG, dLdxyz=None, dLdtheta=None, stream=None):
+    """dLdG: float32 CUDA tensor [8, 3, nz, ny, nx]; accumulates into dLdxyz
+    (float32 [n_atoms, 3]) and dLdtheta (float64 [13]) when given."""
+    import torch
+    g = _cuda_check(dLdG.contiguous(), torch.float32, "dLdG")
+    if dLdxyz is not None:
+        _cuda_check(dLdxyz, torch.float32, "dLdxyz")
+    if dLdtheta is not None:
+        _cuda_check(dLdtheta, torch.float64, "dLdtheta")
+    _check(lib.dock_pocket_map_adjoint(pocket.handle, _dptr(g), _dptr(dLdxyz) if dLdxyz is not None else None,
+                                       _dptr(dLdtheta) if dLdtheta is not None else None, _stream(stream)))
 
 
 def dock_abi_version():

@@ -1428,6 +1428,24 @@ int dock_best_poses(dock_ligands_t L, int32_t n_traj, const float* E_best, const
   return DOCK_OK;
 }
 
+int dock_pocket_map_adjoint(dock_pocket_t p, const float* dLdG, float* dLdxyz, double* dLdtheta,
+                            void* stream) {
+  if (!p || !dLdG) return fail(DOCK_E_ARG, "null argument");
+  if (p->dev.inter_mode != DOCK_INTER_GRID || !p->d_rec)
+    return fail(DOCK_E_ARG, "the map adjoint needs a grid-mode pocket");
+  if (p->dev.preset != DOCK_PRESET_TRIDS) return fail(DOCK_E_ARG, "the map adjoint covers the TRIDS terms");
+  MapAdjArgs a{};
+  a.rec = p->d_rec;
+  a.n_rec = p->n_rec;
+  a.grid = p->dev.grid;
+  type_pair_table(DOCK_PRESET_TRIDS, a.tab);
+  a.lam = dLdG;
+  a.dLdxyz = dLdxyz;
+  a.dLdtheta = dLdtheta;
+  HIP_TRY(launch_map_adjoint(a, reinterpret_cast<hipStream_t>(stream)));
+  return DOCK_OK;
+}
+
 int dock_screen_rank(const float* scores, int64_t n, int32_t stride, int32_t top_k, float* score_out,
                      int32_t* lig_out, void* stream) {
   if (n < 0 || n > (int64_t(1) << 31) - 2) return fail(DOCK_E_ARG, "n must be in [0, 2^31 - 2]");

@@ -105,6 +105,20 @@ struct MapArgs {
   float* M;  // [8][nodes]
 };
 
+// Adjoint of the TRIDS map build: dL/d(receptor xyz) and dL/dtheta for
+// theta = (mu_long, sigma_long, mu_hb, sigma_hb, d_clash_hb, R_0..R_7).
+constexpr int kMapTheta = 5 + kTypes;
+struct MapAdjArgs {
+  const float4* rec;   // xyz, w = bits(type), caller order
+  int n_rec;
+  GridDev grid;
+  TypePair tab[kTypes * kTypes];
+  const float* lam;    // dL/dG [8][3][nodes]
+  float* dLdxyz;       // [n_rec * 3], +=
+  double* dLdtheta;    // [kMapTheta], +=
+};
+hipError_t launch_map_adjoint(const MapAdjArgs& a, hipStream_t s);
+
 // LDS bytes a sampler block of `block` threads needs.
 size_t sample_lds_bytes(int lpp, int apl, int block, int max_pairs);
 size_t score_lds_bytes(int lpp, int apl, int max_pairs);

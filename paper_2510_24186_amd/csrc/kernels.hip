@@ -100,6 +100,120 @@ hipError_t launch_map_build(const MapArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ================================================================ map adjoint
+
+// One workgroup per receptor atom: the nodes of the box around it that lie
+// inside the 10 A cutoff (the same FP32 decisions as map_kernel), every
+// ligand type, the chain rule in FP64.  Per atom: dL/dr written once (no
+// atomics); dL/dtheta reduced in the workgroup, then 13 atomic adds.
+__global__ void __launch_bounds__(256) map_adjoint_kernel(MapAdjArgs a) {
+  __shared__ TypePair stab[kTypes * kTypes];
+  __shared__ double red[256];
+  if (threadIdx.x < kTypes * kTypes) stab[threadIdx.x] = a.tab[threadIdx.x];
+  __syncthreads();
+  const int i = blockIdx.x;
+  const float4 ri = a.rec[i];
+  const int u = __float_as_int(ri.w) & 0xff;
+  const int nx = a.grid.dims[0], ny = a.grid.dims[1], nz = a.grid.dims[2];
+  const long long nodes = (long long)nx * ny * nz;
+  int lo[3], hi[3];
+  const float rr[3] = {ri.x, ri.y, ri.z};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double o = a.grid.origin[c], h = a.grid.spacing;
+    const int n = a.grid.dims[c];
+    lo[c] = max(0, int(floor((double(rr[c]) - 10.0 - o) / h)) - 1);
+    hi[c] = min(n - 1, int(ceil((double(rr[c]) + 10.0 - o) / h)) + 1);
+  }
+  const int bx = hi[0] - lo[0] + 1, by = hi[1] - lo[1] + 1, bz = hi[2] - lo[2] + 1;
+  const long long nbox = (bx > 0 && by > 0 && bz > 0) ? (long long)bx * by * bz : 0;
+  // accumulators: dL/dr (3), theta (13)
+  double acc[3 + kMapTheta];
+#pragma unroll
+  for (int k = 0; k < 3 + kMapTheta; ++k) acc[k] = 0.0;
+  constexpr double kSigL = 1.4142135623730951;   // sigma_long: 2 sigma^2 = 4
+  constexpr double kSigL2 = 2.0, kSigL3 = 2.0 * 1.4142135623730951;
+  constexpr double kSigH2 = 0.09, kSigH3 = 0.027;
+  (void)kSigL;
+  for (long long q = threadIdx.x; q < nbox; q += 256) {
+    const int ix = lo[0] + int(q % bx), iy = lo[1] + int((q / bx) % by), iz = lo[2] + int(q / ((long long)bx * by));
+    const float px = float(double(a.grid.origin[0]) + double(a.grid.spacing) * ix);
+    const float py = float(double(a.grid.origin[1]) + double(a.grid.spacing) * iy);
+    const float pz = float(double(a.grid.origin[2]) + double(a.grid.spacing) * iz);
+    const float d2 = d2_rounded(px - ri.x, py - ri.y, pz - ri.z);
+    if (!(d2 < 100.0f)) continue;
+    const double ex = double(ri.x) - double(px), ey = double(ri.y) - double(py), ez = double(ri.z) - double(pz);
+    const double d = sqrt(ex * ex + ey * ey + ez * ez);
+    const long long node = ((long long)iz * ny + iy) * nx + ix;
+    double dphi = 0.0;
+    for (int t = 0; t < kTypes; ++t) {
+      const TypePair tp = stab[t * kTypes + u];
+      const float* lt = a.lam + (long long)(t * 3) * nodes + node;
+      const double l0 = lt[0], l1 = lt[nodes], l2 = lt[2 * nodes];
+      const bool hb = tp.flags & 1u;
+      // E_long
+      {
+        const double x = d - tp.rsum64 - 3.0;
+        const double g = exp(-0.25 * x * x);
+        const double c = l0 * g * x / kSigL2;
+        dphi += c;
+        acc[3] -= c;
+        acc[4] -= l0 * g * x * x / kSigL3;
+        acc[3 + 5 + t] -= c;
+        acc[3 + 5 + u] -= c;
+      }
+      // E_clash
+      if (d2 < tp.dclash2) {
+        if (d > 0.1) dphi -= l1 / d;
+        const double ddc = l1 / tp.dclash64;
+        if (hb) {
+          acc[3 + 4] += ddc;
+        } else {
+          acc[3 + 5 + t] += ddc;
+          acc[3 + 5 + u] += ddc;
+        }
+      }
+      // E_Hbond
+      if (hb && d2 < 3.4f * 3.4f) {
+        const double x = d - 2.88;
+        const double g = exp(-x * x / 0.18);
+        const double c = l2 * g * x / kSigH2;
+        dphi += c;
+        acc[3 + 2] -= c;
+        acc[3 + 3] -= l2 * g * x * x / kSigH3;
+      }
+    }
+    if (d > 0.0) {
+      acc[0] += dphi * ex / d;
+      acc[1] += dphi * ey / d;
+      acc[2] += dphi * ez / d;
+    }
+  }
+  // workgroup reduction of the 16 accumulators
+  for (int k = 0; k < 3 + kMapTheta; ++k) {
+    red[threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      if (k < 3) {
+        if (a.dLdxyz) a.dLdxyz[3 * i + k] += float(red[0]);
+      } else if (a.dLdtheta && red[0] != 0.0) {
+        atomicAdd(&a.dLdtheta[k - 3], red[0]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_map_adjoint(const MapAdjArgs& a, hipStream_t s) {
+  if (a.n_rec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(map_adjoint_kernel, dim3(a.n_rec), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 // ================================================================ slabs
 
 template <int LPP, int APL>

@@ -241,3 +241,38 @@ def test_adjoint_differentiation_workload(D):
     G.say("C3 sampled: worst E/tol %.3g dLdq/tol %.3g dLdx-vs-FD/tol %.3g (%d FD poses)" % (*worst, n_fd))
     assert worst[0] <= 1.0 and worst[1] <= 1.0 and worst[2] <= 1.0
     assert n_fd >= 12
+
+
+@pytest.mark.parametrize("n_rec,radius,grid", [(12, 5.0, 14), (40, 7.0, 24)])
+def test_map_build_adjoint_against_oracle(D, n_rec, radius, grid):
+    from oracle import map_adjoint as MA
+    pk = tiny_pocket(n=n_rec, radius=radius, grid=grid, seed=7)
+    G.say("map adjoint pocket", n_rec, "atoms, grid", pk.dims)
+    w = G.weights32(P.PRESET_TRIDS)
+    p = G.load_pocket(pk, P.PRESET_TRIDS, w, keep=True)
+    rng = np.random.default_rng(n_rec)
+    lam = rng.normal(size=(8, 3) + tuple(pk.dims[::-1])).astype(np.float32)
+    dx = torch.zeros((n_rec, 3), device="cuda")
+    dth = torch.zeros(13, dtype=torch.float64, device="cuda")
+    D.dock_pocket_map_adjoint(p, torch.tensor(lam, device="cuda"), dx, dth)
+    torch.cuda.synchronize()
+    ref_x, ref_t = MA.map_adjoint(pk, lam.reshape(8, 3, -1).astype(np.float64))
+    gx, gt = dx.cpu().numpy().astype(np.float64), dth.cpu().numpy()
+    ex = np.abs(gx - ref_x).max() / max(1.0, np.abs(ref_x).max())
+    et = np.abs(gt - ref_t) / np.maximum(1.0, np.abs(ref_t))
+    G.say("map adjoint: dL/dr rel err %.3g, dL/dtheta rel err %.3g" % (ex, et.max()))
+    assert ex <= 1e-6
+    assert et.max() <= 1e-9, (MA.THETA_NAMES[int(et.argmax())], gt, ref_t)
+    # outputs accumulate
+    D.dock_pocket_map_adjoint(p, torch.tensor(lam, device="cuda"), dx, dth)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(dth.cpu().numpy(), 2 * gt, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(dx.cpu().numpy(), 2 * gx, rtol=1e-6, atol=1e-6)
+
+
+def test_map_build_adjoint_rejects_other_presets(D):
+    pk = tiny_pocket(n=12, radius=5.0, grid=14, seed=7)
+    p = G.load_pocket(pk, P.PRESET_VINA, G.weights32(P.PRESET_VINA), keep=True)
+    lam = torch.zeros((8, 5) + tuple(pk.dims[::-1]), device="cuda")
+    with pytest.raises(D.DockError):
+        D.dock_pocket_map_adjoint(p, lam)
