@@ -865,8 +865,11 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
       }
     }
     wave_sync();
+    // a pass-layout ligand evaluated with two atoms per lane (a group sized
+    // for a larger ligand of the same call) keeps its records at entry 2p
+    const int pstep = L.n_pass > 0 ? 2 : 1;
     for (int p = r; p < L.n_prec; p += LPP) {
-      const PairRec pr = pairs[p];
+      const PairRec pr = pairs[pstep * p];
       if (pr.w & kPairEmpty) continue;
       const int i = pr.w & 0xff, j = (pr.w >> 8) & 0xff;
       float f[3];

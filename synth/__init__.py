@@ -292,3 +292,34 @@ def vina_weights(rng, w0=(-0.0356, -0.00516, 0.840, -0.0351, -0.587)):
     """Per-term weights drawn around the Vina defaults, ~N(w0, 0.1|w0|)."""
     w0 = np.asarray(w0)
     return (w0 + 0.1 * np.abs(w0) * rng.normal(size=w0.shape)).astype(np.float32)
+
+
+def make_residues(pocket, size=8, seed=0):
+    """Residue index per receptor atom: seeded greedy groups of up to `size`
+    mutually close atoms (a seed atom and its nearest unassigned neighbours
+    within 6 A), numbered in order of creation."""
+    rng = _rng(seed, 7)
+    xyz = np.asarray(pocket.xyz, np.float64)
+    n = len(xyz)
+    res = np.full(n, -1, np.int32)
+    nxt = 0
+    for a in rng.permutation(n):
+        if res[a] >= 0:
+            continue
+        free = np.flatnonzero(res < 0)
+        d = np.linalg.norm(xyz[free] - xyz[a], axis=1)
+        take = free[np.argsort(d, kind="stable")][:size]
+        take = take[np.linalg.norm(xyz[take] - xyz[a], axis=1) < 6.0]
+        res[take] = nxt
+        nxt += 1
+    return res
+
+
+def make_mdn_params(n_ligand_atoms, n_res, K=4, seed=0):
+    """Mixture parameters [n_ligand_atoms, n_res, K, 3] = (pi, mu, sigma):
+    weights from a flat Dirichlet, means U[2.5, 5.5] A, widths U[0.3, 1.0] A."""
+    rng = _rng(seed, 8)
+    pi = rng.dirichlet(np.ones(K), size=(n_ligand_atoms, n_res))
+    mu = rng.uniform(2.5, 5.5, size=(n_ligand_atoms, n_res, K))
+    sig = rng.uniform(0.3, 1.0, size=(n_ligand_atoms, n_res, K))
+    return np.stack([pi, mu, sig], axis=-1).astype(np.float32)
