@@ -98,7 +98,21 @@ typedef struct {
                              cell list of half-cutoff cells (the paper's cutoff
                              pair kernel, Discussion item 4); no maps, no box
                              term, not usable by the differentiable form */
+  const int32_t* residue; /* host [n_atoms] residue index per receptor atom
+                             (0 .. n_res - 1, every index used) or NULL: the
+                             residue geometry of the E_MDN term */
+  float mdn_weight;       /* w_MDN (Methods E_dock: 1.0) */
 } dock_pocket_desc;
+
+/* E_MDN term (Methods, "Scoring functions"): for residue i and ligand atom
+ * j, d_ij = the smallest distance from the atom to the residue's atoms,
+ * P(d) = sum_k pi_k exp(-(d - mu_k)^2 / (2 sigma_k^2)), and
+ * E_MDN = -sum over d_ij < 5 A of P(d_ij); E_dock adds mdn_weight * E_MDN.
+ * The term is active in grid mode when the pocket has residues, mdn_weight
+ * is nonzero and the ligands carry mixture parameters for as many residues
+ * (dock_ligands_set_mdn); the gradient goes through d_ij at the nearest
+ * atom (lowest index on ties).  The network that predicts the parameters is
+ * not part of the library. */
 
 /* Builds the maps on `stream`; the returned handle owns them.  The call
  * returns after enqueueing; the maps are ready when the stream reaches it. */
@@ -151,6 +165,13 @@ int dock_ligand_info(dock_ligands_t L, int32_t lig, dock_ligand_info_t* info);
 /* Integer topology in the caller's atom numbering (host outputs, nullable):
  * type [N], atom_frag [N], frag_parent [F] (-1 root), tors_frag [n_t],
  * tors_atoms [n_t * 2] (a_k, b_k), pairs [n_pairs * 2], bfs [F]. */
+/* Mixture parameters of the E_MDN term for every ligand atom and residue:
+ * params host [total_atoms][n_res][n_gauss][3] = (pi, mu, sigma), atoms in
+ * the caller's order (dock_ligand_desc), sigma > 0, 1 <= n_gauss <= 16.
+ * Copied; replaces earlier parameters.  n_res must match the pockets the
+ * ligands are scored against. */
+int dock_ligands_set_mdn(dock_ligands_t L, int32_t n_res, int32_t n_gauss, const float* params);
+
 int dock_ligand_topology(dock_ligands_t L, int32_t lig, uint8_t* type, int32_t* atom_frag,
                          int32_t* frag_parent, int32_t* tors_frag, int32_t* tors_atoms,
                          int32_t* pairs, int32_t* bfs);

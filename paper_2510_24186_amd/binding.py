@@ -33,7 +33,7 @@ _f32 = C.c_float
 class PocketDesc(C.Structure):
     _fields_ = [("n_atoms", _i32), ("xyz", _p), ("type", _p), ("origin", _f32 * 3),
                 ("spacing", _f32), ("dims", _i32 * 3), ("preset", _i32), ("weights", _p),
-                ("keep_per_term", _i32), ("inter_mode", _i32)]
+                ("keep_per_term", _i32), ("inter_mode", _i32), ("residue", _p), ("mdn_weight", _f32)]
 
 
 class LigandDesc(C.Structure):
@@ -100,6 +100,7 @@ _sig("dock_free_run", C.c_int, _p)
 _sig("dock_philox", C.c_int, _p, C.c_uint32, C.c_uint32, C.c_int64, _p, _p)
 _sig("dock_screen_rank", C.c_int, _p, C.c_int64, _i32, _i32, _p, _p, _p)
 _sig("dock_pocket_map_adjoint", C.c_int, _p, _p, _p, _p, _p)
+_sig("dock_ligands_set_mdn", C.c_int, _p, _i32, _i32, _p)
 _sig("dock_best_poses", C.c_int, _p, _i32, _p, _p, _i32, _i32, _f32, _f32, _p, _p, _p, _p, _p, _i32,
      _p, _p)
 
@@ -175,7 +176,8 @@ class Pocket:
 
 
 def dock_load_pocket(xyz, types, origin, spacing, dims, preset=PRESET_TRIDS, weights=None,
-                     keep_per_term=False, inter_mode=INTER_GRID, stream=None):
+                     keep_per_term=False, inter_mode=INTER_GRID, residue=None, mdn_weight=1.0,
+                     stream=None):
     xyz = _np(xyz, np.float32).reshape(-1, 3)
     types = _np(types, np.uint8)
     d = PocketDesc()
@@ -190,6 +192,9 @@ def dock_load_pocket(xyz, types, origin, spacing, dims, preset=PRESET_TRIDS, wei
     d.weights = _ptr(w)
     d.keep_per_term = int(bool(keep_per_term))
     d.inter_mode = int(inter_mode)
+    res = None if residue is None else _np(residue, np.int32)
+    d.residue = _ptr(res)
+    d.mdn_weight = float(mdn_weight)
     h = _p()
     _check(lib.dock_load_pocket(C.byref(d), _stream(stream), C.byref(h)))
     pr = _i32()
@@ -265,6 +270,14 @@ def dock_load_ligands(atom_off, element, n_h, xyz, bond_off, bonds, rotatable, b
     n, ma, mt, ta = _i32(), _i32(), _i32(), C.c_int64()
     _check(lib.dock_ligands_count(h, C.byref(n), C.byref(ma), C.byref(mt), C.byref(ta)))
     return Ligands(h, n.value, ma.value, mt.value, ta.value, bool(host_only))
+
+
+def dock_ligands_set_mdn(L, params):
+    """params: [total_atoms, n_res, n_gauss, 3] (pi, mu, sigma), caller atom order."""
+    a = _np(params, np.float32)
+    if a.ndim != 4 or a.shape[3] != 3:
+        raise ValueError("params must be [total_atoms, n_res, n_gauss, 3]")
+    _check(lib.dock_ligands_set_mdn(L.handle, a.shape[1], a.shape[2], _ptr(a)))
 
 
 def dock_ligand_info(L, i):

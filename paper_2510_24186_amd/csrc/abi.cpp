@@ -61,7 +61,24 @@ struct dock_pocket_s {
   float4* d_sorted = nullptr;   // direct mode
   int* d_cells = nullptr;
   float2* d_tp = nullptr;
+  float4* d_res_xyz = nullptr;  // E_MDN residue geometry
+  int2* d_res_range = nullptr;
+  int* d_mcell_start = nullptr;
+  int* d_mcell_res = nullptr;
 };
+
+static void free_pocket_device(dock_pocket_s* p) {
+  dev_free(p->d_rec);
+  dev_free(p->d_M);
+  dev_free(p->d_G);
+  dev_free(p->d_sorted);
+  dev_free(p->d_cells);
+  dev_free(p->d_tp);
+  dev_free(p->d_res_xyz);
+  dev_free(p->d_res_range);
+  dev_free(p->d_mcell_start);
+  dev_free(p->d_mcell_res);
+}
 
 struct dock_ligands_s {
   std::vector<LigandHost> host;
@@ -74,7 +91,11 @@ struct dock_ligands_s {
   FragDev* d_frags = nullptr;
   TorsDev* d_tors = nullptr;
   PairRec* d_pairs = nullptr;
-  LigandArrays arrays() const { return LigandArrays{d_ligs, d_atoms, d_frags, d_tors, d_pairs}; }
+  float4* d_mdn = nullptr;   // E_MDN mixture parameters (see LigandArrays)
+  int mdn_res = 0, mdn_k = 0;
+  LigandArrays arrays() const {
+    return LigandArrays{d_ligs, d_atoms, d_frags, d_tors, d_pairs, d_mdn, mdn_res, mdn_k};
+  }
 };
 
 // Device tables of PocketDev, cached per ordered list of pocket handles.
@@ -217,16 +238,45 @@ int dock_load_pocket(const dock_pocket_desc* d, void* stream, dock_pocket_t* out
     std::memcpy(&rec[i].w, &bits, 4);
   }
   auto cleanup = [&](int code, const std::string& m) {
-    dev_free(p->d_rec);
-    dev_free(p->d_M);
-    dev_free(p->d_G);
-    dev_free(p->d_sorted);
-    dev_free(p->d_cells);
-    dev_free(p->d_tp);
+    free_pocket_device(p);
     delete p;
     return fail(code, m);
   };
   pd.inter_mode = d->inter_mode;
+  // E_MDN residue geometry
+  pd.mdn_res = 0;
+  pd.mdn_w = 0.f;
+  if (d->residue && d->n_atoms > 0) {
+    if (!std::isfinite(d->mdn_weight)) return cleanup(DOCK_E_ARG, "non-finite mdn_weight");
+    MdnGeometry mg;
+    std::string err;
+    const int rc = build_mdn_geometry(d->n_atoms, d->xyz, d->residue, mg, err);
+    if (rc != DOCK_OK) return cleanup(rc, err);
+    hipError_t e = dev_alloc(&p->d_res_xyz, mg.res_xyz.size());
+    if (e == hipSuccess) e = dev_alloc(&p->d_res_range, mg.res_range.size());
+    if (e == hipSuccess) e = dev_alloc(&p->d_mcell_start, mg.cell_start.size());
+    if (e == hipSuccess) e = dev_alloc(&p->d_mcell_res, std::max<size_t>(1, mg.cell_res.size()));
+    if (e != hipSuccess) return cleanup(DOCK_E_OOM, std::string("residue geometry allocation: ") + hipGetErrorString(e));
+    e = hipMemcpy(p->d_res_xyz, mg.res_xyz.data(), sizeof(float4) * mg.res_xyz.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_res_range, mg.res_range.data(), sizeof(int2) * mg.res_range.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_mcell_start, mg.cell_start.data(), sizeof(int) * mg.cell_start.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !mg.cell_res.empty())
+      e = hipMemcpy(p->d_mcell_res, mg.cell_res.data(), sizeof(int) * mg.cell_res.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(DOCK_E_HIP, std::string("residue geometry upload: ") + hipGetErrorString(e));
+    pd.mdn_res = mg.n_res;
+    pd.mdn_w = d->mdn_weight;
+    pd.res_xyz = p->d_res_xyz;
+    pd.res_range = p->d_res_range;
+    pd.mcell_start = p->d_mcell_start;
+    pd.mcell_res = p->d_mcell_res;
+    for (int c = 0; c < 3; ++c) {
+      pd.mcell_origin[c] = mg.origin[c];
+      pd.mcell_dims[c] = mg.dims[c];
+    }
+    pd.inv_mcell = 1.0f / kMdnCell;
+  }
   if (d->inter_mode == DOCK_INTER_DIRECT) {
     // cell list: cells of half the largest cutoff over the receptor's bounds
     const double cell = (d->preset == DOCK_PRESET_TRIDS ? 10.0 : 8.0) / 2.0;
@@ -343,12 +393,7 @@ int dock_free_pocket(dock_pocket_t p) {
   if (!p) return DOCK_OK;
   drop_tables_with(p);
   (void)hipDeviceSynchronize();
-  dev_free(p->d_rec);
-  dev_free(p->d_M);
-  dev_free(p->d_G);
-  dev_free(p->d_sorted);
-  dev_free(p->d_cells);
-  dev_free(p->d_tp);
+  free_pocket_device(p);
   delete p;
   return DOCK_OK;
 }
@@ -361,6 +406,7 @@ static void free_ligand_device(dock_ligands_s* L) {
   dev_free(L->d_frags);
   dev_free(L->d_tors);
   dev_free(L->d_pairs);
+  dev_free(L->d_mdn);
 }
 
 static int bit_length(int v) {
@@ -621,6 +667,43 @@ int dock_ligand_topology(dock_ligands_t L, int32_t lig, uint8_t* type, int32_t* 
   return DOCK_OK;
 }
 
+int dock_ligands_set_mdn(dock_ligands_t L, int32_t n_res, int32_t n_gauss, const float* params) {
+  if (!L || !params) return fail(DOCK_E_ARG, "null argument");
+  if (L->host_only) return fail(DOCK_E_ARG, "ligand handle was loaded host_only");
+  if (n_res < 1 || n_gauss < 1 || n_gauss > 16) return fail(DOCK_E_ARG, "n_res >= 1 and 1 <= n_gauss <= 16");
+  const size_t per_atom = size_t(n_res) * n_gauss;
+  if (size_t(L->total_atoms) * per_atom > (size_t(1) << 31)) return fail(DOCK_E_LIMIT, "mixture table too large");
+  std::vector<float4> tab(size_t(L->total_atoms) * per_atom);
+  constexpr double kLog2e = 1.4426950408889634;
+  for (int l = 0; l < L->n; ++l) {
+    const LigandHost& H = L->host[l];
+    const LigDev& g = L->h_ligs[l];
+    for (int na = 0; na < H.n_atoms; ++na) {
+      const size_t src = (size_t(g.atom_off) + size_t(H.dfs_atom[na])) * per_atom;
+      const size_t dst = (size_t(g.atom_off) + size_t(na)) * per_atom;
+      for (size_t q = 0; q < per_atom; ++q) {
+        const double pi = params[3 * (src + q)], mu = params[3 * (src + q) + 1], sig = params[3 * (src + q) + 2];
+        if (!std::isfinite(pi) || !std::isfinite(mu) || !(sig > 0.0) || !std::isfinite(sig))
+          return fail(DOCK_E_ARG, "mixture parameters must be finite with sigma > 0");
+        tab[dst + q] = make_float4(float(pi), float(mu), float(kLog2e / (2.0 * sig * sig)), float(1.0 / (sig * sig)));
+      }
+    }
+  }
+  float4* d = nullptr;
+  hipError_t e = dev_alloc(&d, std::max<size_t>(1, tab.size()));
+  if (e == hipSuccess && !tab.empty()) e = hipMemcpy(d, tab.data(), sizeof(float4) * tab.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    dev_free(d);
+    return fail(DOCK_E_HIP, std::string("mixture table upload: ") + hipGetErrorString(e));
+  }
+  (void)hipDeviceSynchronize();
+  dev_free(L->d_mdn);
+  L->d_mdn = d;
+  L->mdn_res = n_res;
+  L->mdn_k = n_gauss;
+  return DOCK_OK;
+}
+
 int dock_ligands_count(dock_ligands_t L, int32_t* n_ligands, int32_t* max_atoms, int32_t* max_tors,
                        int64_t* total_atoms) {
   if (!L) return fail(DOCK_E_ARG, "null argument");
@@ -651,7 +734,23 @@ static int check_pockets(const dock_pocket_t* pockets, int n_pockets, dock_ligan
   for (int i = 0; i < L->n; ++i)
     if (L->host[i].pocket >= n_pockets) return fail(DOCK_E_ARG, "ligand pocket index out of range");
   if (L->host_only) return fail(DOCK_E_ARG, "ligand handle was loaded host_only");
+  for (int i = 0; i < n_pockets; ++i) {
+    const PocketDev& pd = pockets[i]->dev;
+    if (pd.mdn_res > 0 && pd.mdn_w != 0.f && L->d_mdn && L->mdn_res != pd.mdn_res)
+      return fail(DOCK_E_ARG, "E_MDN parameters cover a different number of residues than the pocket");
+  }
   return DOCK_OK;
+}
+
+// Kernel mode of a call: direct pair sums, grid maps with the E_MDN term
+// (some pocket has residues and a weight, and the ligands carry mixture
+// parameters), or grid maps only.
+static int eval_mode(const dock_pocket_t* pockets, int n_pockets, dock_ligands_t L) {
+  if (pockets[0]->dev.inter_mode == DOCK_INTER_DIRECT) return kModeDirect;
+  if (L->d_mdn)
+    for (int i = 0; i < n_pockets; ++i)
+      if (pockets[i]->dev.mdn_res > 0 && pockets[i]->dev.mdn_w != 0.f) return kModeGridMdn;
+  return kModeGrid;
 }
 
 int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L, int64_t n_poses,
@@ -692,7 +791,7 @@ int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligand
   a.xyz = xyz_out;
   a.xyz_stride = xyz_stride;
   a.max_pairs = L->max_pairs;
-  HIP_TRY(launch_score(a, lpp, apl, pockets[0]->dev.inter_mode == DOCK_INTER_DIRECT,
+  HIP_TRY(launch_score(a, lpp, apl, eval_mode(pockets, n_pockets, L),
                        reinterpret_cast<hipStream_t>(stream)));
   return DOCK_OK;
 }
@@ -813,7 +912,7 @@ struct dock_run_s {
   dock_ligands_t L = nullptr;
   std::vector<dock_pocket_t> pockets;
   const PocketDev* table = nullptr;
-  bool direct = false;
+  int mode = kModeGrid;             // kernel mode (eval_mode)
   dock_sample_params p{};
   int n_lig = 0, T = 0, q_stride = 0, step = 0, trace_cap = 0;
   float *q_cur = nullptr, *E_cur = nullptr, *q_best = nullptr, *E_best = nullptr, *trace = nullptr;
@@ -860,7 +959,7 @@ static hipError_t timed_launch(dock_run_s* r, const SampleArgs& a, int bucket, i
     eb = pool_event(r);
     if (ea) (void)hipEventRecord(ea, s);
   }
-  hipError_t e = launch_sample(a, lpp, apl, grid, block, r->direct, s);
+  hipError_t e = launch_sample(a, lpp, apl, grid, block, r->mode, s);
   if (r->recording && ea && eb) {
     (void)hipEventRecord(eb, s);
     dock_run_s::Launch L;
@@ -1051,7 +1150,7 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   if (!r) return fail(DOCK_E_OOM, "host allocation");
   r->L = L;
   r->pockets.assign(pockets, pockets + n_pockets);
-  r->direct = pockets[0]->dev.inter_mode == DOCK_INTER_DIRECT;
+  r->mode = eval_mode(pockets, n_pockets, L);
   r->p = *p;
   r->n_lig = L->n;
   r->T = p->n_traj;
@@ -1134,7 +1233,7 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
       B.n_items = int(items.size()) - B.item_off;
       const size_t lds = sample_lds_bytes(B.lpp, B.apl, B.block, B.max_pairs);
       if (lds > 64 * 1024) return bail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
-      const int per_cu = sample_max_blocks_per_cu(B.lpp, B.apl, B.block, r->direct, lds);
+      const int per_cu = sample_max_blocks_per_cu(B.lpp, B.apl, B.block, r->mode, lds);
       B.grid = std::min(B.n_items, per_cu * n_cu);
     }
   }

@@ -148,6 +148,11 @@ DK_INLINE float2 ldg(const float2* p) {
   const f32x2_t v = *(const __attribute__((address_space(1))) f32x2_t*)p;
   return make_float2(v.x, v.y);
 }
+typedef int i32x2_t __attribute__((ext_vector_type(2)));
+DK_INLINE int2 ldg(const int2* p) {
+  const i32x2_t v = *(const __attribute__((address_space(1))) i32x2_t*)p;
+  return make_int2(v.x, v.y);
+}
 
 // exp(x) on the hardware exp2 (v_exp_f32): callers pass x * log2(e) already
 // folded into their constants.  Relative error ~1e-6 for the Gaussian
@@ -412,6 +417,68 @@ DK_INLINE void inter_direct(const PocketDev& pk, int preset, const float* w, int
       }
     }
   }
+}
+
+// ------------------------------------------------------------------ E_MDN
+// Mixture term of one ligand atom at x (Methods, E_MDN): the residues listed
+// for x's lattice cell, the nearest atom of each, and for d < 5 A the
+// mixture P(d) from the atom's parameters for that residue (float4 pi, mu,
+// log2(e) / (2 sigma^2), 1 / sigma^2).  Adds -w P to e and its gradient to g.
+struct MdnArg {
+  const float4* par;  // this ligand's table: [atom (DFS)][residue][gaussian]
+  int n_res, k;
+};
+
+DK_INLINE void mdn_term(const PocketDev& pk, const MdnArg& m, int atom, float px, float py, float pz, float& e,
+                        float& gx, float& gy, float& gz) {
+  int ic[3];
+  const float p[3] = {px, py, pz};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ic[c] = int(floorf((p[c] - pk.mcell_origin[c]) * pk.inv_mcell));
+  if (ic[0] < 0 || ic[1] < 0 || ic[2] < 0 || ic[0] >= pk.mcell_dims[0] || ic[1] >= pk.mcell_dims[1] ||
+      ic[2] >= pk.mcell_dims[2])
+    return;  // farther than the cutoff from every receptor atom
+  const int cell = (ic[2] * pk.mcell_dims[1] + ic[1]) * pk.mcell_dims[0] + ic[0];
+  const int b = ldg(pk.mcell_start + cell), end = ldg(pk.mcell_start + cell + 1);
+  const float4* par_atom = m.par + size_t(atom) * m.n_res * m.k;
+  float es = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+  for (int q = b; q < end; ++q) {
+    const int res = ldg(pk.mcell_res + q);
+    const int2 rng = ldg(pk.res_range + res);
+    float best = INFINITY, bx = 0.f, by = 0.f, bz = 0.f;
+    for (int a = rng.x; a < rng.y; ++a) {
+      const float4 r = ldg(pk.res_xyz + a);
+      const float dx = px - r.x, dy = py - r.y, dz = pz - r.z;
+      const float d2 = dx * dx + dy * dy + dz * dz;
+      if (d2 < best) {
+        best = d2;
+        bx = dx;
+        by = dy;
+        bz = dz;
+      }
+    }
+    if (!(best < kMdnCutoff * kMdnCutoff)) continue;
+    const float inv_d = best > 0.f ? __builtin_amdgcn_rsqf(best) : 0.f;
+    const float d = best * inv_d;
+    const float4* pr = par_atom + size_t(res) * m.k;
+    float P = 0.f, dP = 0.f;
+    for (int k = 0; k < m.k; ++k) {
+      const float4 g = ldg(pr + k);
+      const float x = d - g.y;
+      const float v = g.x * exp2_hw(-(x * x) * g.z);
+      P += v;
+      dP -= v * x * g.w;
+    }
+    es -= P;
+    const float c = -dP * inv_d;
+    sx += c * bx;
+    sy += c * by;
+    sz += c * bz;
+  }
+  e += pk.mdn_w * es;
+  gx += pk.mdn_w * sx;
+  gy += pk.mdn_w * sy;
+  gz += pk.mdn_w * sz;
 }
 
 // ------------------------------------------------------------------ pose evaluation
@@ -767,11 +834,17 @@ DK_INLINE float pair_force(const LaneLig<APL>& L, const PairRec& pr, const float
 }
 
 // One evaluation of E and dE/dq at the pose whose DOF r is held by lane r.
-// Optionally leaves world coordinates and atom gradients in xo/go.
-template <int LPP, int APL, bool WANT_X = false, bool DIRECT = false>
+// Optionally leaves world coordinates and atom gradients in xo/go; adds the
+// E_MDN term when mdn.par is set.
+// MODE: 0 receptor terms from the grid maps, 1 summed pair by pair over the
+// receptor cell list, 2 grid maps plus the E_MDN term.
+constexpr int kModeGrid = 0, kModeDirect = 1, kModeGridMdn = 2;
+
+template <int LPP, int APL, bool WANT_X = false, int MODE = kModeGrid>
 DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& pk,
                             const PairRec* __restrict__ pairs, const GroupSlab& S, int r,
-                            float (*xo)[3] = nullptr, float (*go)[3] = nullptr) {
+                            float (*xo)[3] = nullptr, float (*go)[3] = nullptr,
+                            const MdnArg& mdn = MdnArg{nullptr, 0, 0}) {
   LaneLig<APL> L = Lin;
   launder(L);
   // ---- atoms: place, interpolate, publish coordinates to the slab
@@ -782,7 +855,7 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
   for (int s = 0; s < APL; ++s) {
     const int atom = APL * r + s;
     if (atom < L.n_atoms) {
-      if (DIRECT) {
+      if (MODE == kModeDirect) {
         float ei;
         inter_direct(pk, L.preset, L.w, L.atype[s], x[s][0], x[s][1], x[s][2], ei, g[s][0], g[s][1],
                      g[s][2]);
@@ -795,6 +868,8 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
         g[s][1] = tl.gy;
         g[s][2] = tl.gz;
       }
+      if (MODE == kModeGridMdn && mdn.par)
+        mdn_term(pk, mdn, atom, x[s][0], x[s][1], x[s][2], e_lane, g[s][0], g[s][1], g[s][2]);
       S.xs[atom] = make_float4(x[s][0], x[s][1], x[s][2], 0.f);
     } else {
       g[s][0] = g[s][1] = g[s][2] = 0.f;

@@ -82,7 +82,34 @@ struct PocketDev {
   float cell_origin[3];
   float inv_cell;
   int cell_dims[3];
+  // E_MDN residue geometry (mdn_res = 0: no term): receptor atoms sorted by
+  // residue, [begin, end) per residue, and per cell of a fine lattice over
+  // the receptor box grown by the 5 A cutoff the residues that come within
+  // 5 A of the cell
+  int mdn_res;
+  float mdn_w;
+  const float4* res_xyz;
+  const int2* res_range;
+  const int* mcell_start;
+  const int* mcell_res;
+  float mcell_origin[3];
+  float inv_mcell;
+  int mcell_dims[3];
 };
+
+constexpr float kMdnCutoff = 5.0f;
+constexpr float kMdnCell = 1.5f;
+
+// Host build of the E_MDN residue geometry.
+struct MdnGeometry {
+  std::vector<float4> res_xyz;
+  std::vector<int2> res_range;
+  std::vector<int> cell_start, cell_res;
+  float origin[3];
+  int dims[3];
+  int n_res = 0;
+};
+int build_mdn_geometry(int n_atoms, const float* xyz, const int32_t* residue, MdnGeometry& g, std::string& err);
 
 // ---------------------------------------------------------------- host side
 

@@ -13,6 +13,10 @@ struct LigandArrays {
   const FragDev* frags;
   const TorsDev* tors;
   const PairRec* pairs;
+  // E_MDN mixture parameters, float4 (pi, mu, log2(e) / (2 sigma^2),
+  // 1 / sigma^2) per [atom (DFS, global)][residue][gaussian]; null if none
+  const float4* mdn;
+  int mdn_res, mdn_k;
 };
 
 struct ScoreArgs {
@@ -124,8 +128,9 @@ size_t sample_lds_bytes(int lpp, int apl, int block, int max_pairs);
 size_t score_lds_bytes(int lpp, int apl, int max_pairs);
 
 hipError_t launch_map_build(const MapArgs& a, hipStream_t s);
-hipError_t launch_score(const ScoreArgs& a, int lpp, int apl, bool direct, hipStream_t s);
-hipError_t launch_sample(const SampleArgs& a, int lpp, int apl, int grid, int block, bool direct,
+// mode: 0 grid maps, 1 direct pair sums, 2 grid maps + E_MDN
+hipError_t launch_score(const ScoreArgs& a, int lpp, int apl, int mode, hipStream_t s);
+hipError_t launch_sample(const SampleArgs& a, int lpp, int apl, int grid, int block, int mode,
                          hipStream_t s);
 hipError_t launch_best(const BestArgs& a, hipStream_t s);
 
@@ -147,6 +152,6 @@ hipError_t launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, long lon
                          hipStream_t s);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
 hipError_t launch_add_int(int* p, int v, hipStream_t s);
-int sample_max_blocks_per_cu(int lpp, int apl, int block, bool direct, size_t lds);
+int sample_max_blocks_per_cu(int lpp, int apl, int block, int mode, size_t lds);
 
 }  // namespace dock

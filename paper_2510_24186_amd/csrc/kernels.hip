@@ -248,9 +248,20 @@ size_t sample_lds_bytes(int lpp, int apl, int block, int max_pairs) {
   return pair_bytes(max_pairs) + size_t(gpb) * slab_bytes(lpp, apl) + 16;
 }
 
+// E_MDN parameters of one ligand when the term is active for its pocket.
+DK_INLINE MdnArg mdn_for(const LigandArrays& A, const LigDev& lg, const PocketDev& pk) {
+  MdnArg m{nullptr, 0, 0};
+  if (A.mdn && pk.mdn_res > 0 && pk.mdn_w != 0.f && A.mdn_res == pk.mdn_res) {
+    m.par = A.mdn + size_t(lg.atom_off) * A.mdn_res * A.mdn_k;
+    m.n_res = A.mdn_res;
+    m.k = A.mdn_k;
+  }
+  return m;
+}
+
 // ================================================================ score
 
-template <int LPP, int APL, bool DIRECT>
+template <int LPP, int APL, int MODE>
 __global__ void __launch_bounds__(64) score_kernel(ScoreArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int GPB = 64 / LPP;
@@ -273,7 +284,7 @@ __global__ void __launch_bounds__(64) score_kernel(ScoreArgs a) {
   wave_sync();
   const float q = r < lg.n_dof ? a.q[pose * a.q_stride + r] : 0.f;
   float xo[APL][3], go[APL][3];
-  const EvalOut o = eval_pose<LPP, APL, true, DIRECT>(L, q, pk, gp, S, r, xo, go);
+  const EvalOut o = eval_pose<LPP, APL, true, MODE>(L, q, pk, gp, S, r, xo, go, mdn_for(a.L, lg, pk));
   if (r == 0) a.E[pose] = o.E;
   if (a.dEdq && r < lg.n_dof) a.dEdq[pose * a.q_stride + r] = o.g;
   if (a.xyz) {
@@ -290,27 +301,28 @@ __global__ void __launch_bounds__(64) score_kernel(ScoreArgs a) {
   }
 }
 
-template <bool DIRECT>
+template <int MODE>
 static hipError_t launch_score_t(const ScoreArgs& a, int lpp, int apl, unsigned blocks, size_t lds,
                                  hipStream_t s) {
   if (lpp == 16 && apl == 1)
-    hipLaunchKernelGGL((score_kernel<16, 1, DIRECT>), dim3(blocks), dim3(64), lds, s, a);
+    hipLaunchKernelGGL((score_kernel<16, 1, MODE>), dim3(blocks), dim3(64), lds, s, a);
   else if (lpp == 32 && apl == 1)
-    hipLaunchKernelGGL((score_kernel<32, 1, DIRECT>), dim3(blocks), dim3(64), lds, s, a);
+    hipLaunchKernelGGL((score_kernel<32, 1, MODE>), dim3(blocks), dim3(64), lds, s, a);
   else if (lpp == 64 && apl == 1)
-    hipLaunchKernelGGL((score_kernel<64, 1, DIRECT>), dim3(blocks), dim3(64), lds, s, a);
+    hipLaunchKernelGGL((score_kernel<64, 1, MODE>), dim3(blocks), dim3(64), lds, s, a);
   else
-    hipLaunchKernelGGL((score_kernel<64, 2, DIRECT>), dim3(blocks), dim3(64), lds, s, a);
+    hipLaunchKernelGGL((score_kernel<64, 2, MODE>), dim3(blocks), dim3(64), lds, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_score(const ScoreArgs& a, int lpp, int apl, bool direct, hipStream_t s) {
+hipError_t launch_score(const ScoreArgs& a, int lpp, int apl, int mode, hipStream_t s) {
   const int gpb = 64 / lpp;
   const unsigned blocks = unsigned((a.n_poses + gpb - 1) / gpb);
   const size_t lds = score_lds_bytes(lpp, apl, a.max_pairs);
   if (blocks == 0) return hipSuccess;
-  return direct ? launch_score_t<true>(a, lpp, apl, blocks, lds, s)
-                : launch_score_t<false>(a, lpp, apl, blocks, lds, s);
+  if (mode == kModeDirect) return launch_score_t<kModeDirect>(a, lpp, apl, blocks, lds, s);
+  if (mode == kModeGridMdn) return launch_score_t<kModeGridMdn>(a, lpp, apl, blocks, lds, s);
+  return launch_score_t<kModeGrid>(a, lpp, apl, blocks, lds, s);
 }
 
 // ================================================================ differentiable form
@@ -416,8 +428,9 @@ DK_INLINE float wrap_clamp(float q, int r, const LaneLig<APL>& L) {
   return wrap_angle(q);
 }
 
-template <int LPP, int APL, bool DIRECT>
-DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const PocketDev& pk, const PairRec* pairs,
+template <int LPP, int APL, int MODE>
+DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const PocketDev& pk, const MdnArg& mdn,
+                        const PairRec* pairs,
                         const GroupSlab& S, int lig, int traj, int r) {
   const size_t ti = size_t(lig) * a.n_traj + traj;
   const uint32_t k0 = uint32_t(lig), k1 = a.seed;
@@ -439,7 +452,7 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const Pocket
   if (a.init) {
     const uint4 w = philox4x32_10(make_uint4(uint32_t(traj), 0u, 0u, uint32_t(r >> 2)), k0, k1);
     const float q = dof ? L.lo + (L.hi - L.lo) * u01(pick4(w, r & 3)) : 0.f;
-    const EvalOut o = eval_pose<LPP, APL, false, DIRECT>(L, q, pk, pairs, S, r);
+    const EvalOut o = eval_pose<LPP, APL, false, MODE>(L, q, pk, pairs, S, r, nullptr, nullptr, mdn);
     record(q, o.g, o.E);
     if (dof) {
       a.q_cur[ti * qs + r] = q;
@@ -468,7 +481,7 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const Pocket
       // energy of the refined pose: one evaluation site, n_local + 1 calls
       float m = 0.f, v = 0.f, b1t = 1.f, b2t = 1.f;
       for (int t = 0;; ++t) {
-        const EvalOut o = eval_pose<LPP, APL, false, DIRECT>(L, qn, pk, pairs, S, r);
+        const EvalOut o = eval_pose<LPP, APL, false, MODE>(L, qn, pk, pairs, S, r, nullptr, nullptr, mdn);
         record(qn, o.g, o.E);
         E = o.E;
         if (t == a.n_local) break;
@@ -504,7 +517,7 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const Pocket
       bool first = true;
       E = 0.f;
       for (;;) {
-        const EvalOut o = eval_pose<LPP, APL, false, DIRECT>(L, qtry, pk, pairs, S, r);
+        const EvalOut o = eval_pose<LPP, APL, false, MODE>(L, qtry, pk, pairs, S, r, nullptr, nullptr, mdn);
         record(qtry, o.g, o.E);
         if (first) {
           E = o.E;
@@ -555,7 +568,7 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const Pocket
 
 // Three waves per SIMD: the register budget (168) that the step loop fits
 // without spilling.
-template <int LPP, int APL, int BLOCK, bool DIRECT>
+template <int LPP, int APL, int BLOCK, int MODE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) sample_kernel(SampleArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int GPB = BLOCK / LPP;
@@ -589,16 +602,16 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
       const PocketDev pk = a.pockets[lg.pocket];
       LaneLig<APL> L;
       load_lane_lig<LPP, APL>(L, lg, a.L.ligs + lig, a.L.atoms, a.L.frags, a.L.tors, pk, r);
-      run_traj<LPP, APL, DIRECT>(a, L, pk, sp, S, lig, traj, r);
+      run_traj<LPP, APL, MODE>(a, L, pk, mdn_for(a.L, lg, pk), sp, S, lig, traj, r);
     }
     __syncthreads();
   }
 }
 
-template <int LPP, int APL, int BLOCK, bool DIRECT>
+template <int LPP, int APL, int BLOCK, int MODE>
 static hipError_t launch_sample_t(const SampleArgs& a, int grid, hipStream_t s) {
   const size_t lds = sample_lds_bytes(LPP, APL, BLOCK, a.max_pairs);
-  hipLaunchKernelGGL((sample_kernel<LPP, APL, BLOCK, DIRECT>), dim3(grid), dim3(BLOCK), lds, s, a);
+  hipLaunchKernelGGL((sample_kernel<LPP, APL, BLOCK, MODE>), dim3(grid), dim3(BLOCK), lds, s, a);
   return hipGetLastError();
 }
 
@@ -606,26 +619,37 @@ static hipError_t launch_sample_t(const SampleArgs& a, int grid, hipStream_t s) 
   X(16, 1, 64) X(32, 1, 64) X(64, 1, 64) X(64, 2, 64) X(16, 1, 128) X(32, 1, 128) \
       X(64, 1, 128) X(64, 2, 128) X(16, 1, 256) X(32, 1, 256) X(64, 1, 256) X(64, 2, 256)
 
-hipError_t launch_sample(const SampleArgs& a, int lpp, int apl, int grid, int block, bool direct,
+hipError_t launch_sample(const SampleArgs& a, int lpp, int apl, int grid, int block, int mode,
                          hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-#define X(L, A, B)                                                                   \
-  if (lpp == L && apl == A && block == B)                                            \
-    return direct ? launch_sample_t<L, A, B, true>(a, grid, s) : launch_sample_t<L, A, B, false>(a, grid, s);
+#define X(L, A, B)                                                                     \
+  if (lpp == L && apl == A && block == B) {                                            \
+    if (mode == kModeDirect) return launch_sample_t<L, A, B, kModeDirect>(a, grid, s); \
+    if (mode == kModeGridMdn) return launch_sample_t<L, A, B, kModeGridMdn>(a, grid, s); \
+    return launch_sample_t<L, A, B, kModeGrid>(a, grid, s);                            \
+  }
   DOCK_SAMPLE_CASES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-int sample_max_blocks_per_cu(int lpp, int apl, int block, bool direct, size_t lds) {
+template <int L, int A, int B>
+static int blocks_per_cu(int mode, size_t lds) {
   int n = 0;
-#define X(L, A, B)                                                                                 \
-  if (lpp == L && apl == A && block == B) {                                                        \
-    hipError_t e = direct ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_kernel<L, A, B, true>, B, lds) \
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_kernel<L, A, B, false>, B, lds); \
-    if (e != hipSuccess) n = 1;                                                                    \
-    return n > 0 ? n : 1;                                                                          \
-  }
+  hipError_t e;
+  if (mode == kModeDirect)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_kernel<L, A, B, kModeDirect>, B, lds);
+  else if (mode == kModeGridMdn)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_kernel<L, A, B, kModeGridMdn>, B, lds);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_kernel<L, A, B, kModeGrid>, B, lds);
+  if (e != hipSuccess) n = 1;
+  return n > 0 ? n : 1;
+}
+
+int sample_max_blocks_per_cu(int lpp, int apl, int block, int mode, size_t lds) {
+#define X(L, A, B) \
+  if (lpp == L && apl == A && block == B) return blocks_per_cu<L, A, B>(mode, lds);
   DOCK_SAMPLE_CASES(X)
 #undef X
   return 1;

@@ -375,3 +375,98 @@ PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vec
 }
 
 }  // namespace dock
+
+namespace dock {
+
+int build_mdn_geometry(int n, const float* xyz, const int32_t* residue, MdnGeometry& g, std::string& err) {
+  g = MdnGeometry();
+  if (n <= 0) return DOCK_OK;
+  int n_res = 0;
+  for (int a = 0; a < n; ++a) {
+    if (residue[a] < 0) {
+      err = "negative residue index";
+      return DOCK_E_ARG;
+    }
+    n_res = std::max(n_res, residue[a] + 1);
+  }
+  std::vector<int> count(n_res, 0);
+  for (int a = 0; a < n; ++a) ++count[residue[a]];
+  for (int i = 0; i < n_res; ++i)
+    if (count[i] == 0) {
+      err = "residue indices must cover 0 .. n_res - 1";
+      return DOCK_E_ARG;
+    }
+  g.n_res = n_res;
+  // atoms grouped by residue, in increasing atom index within a residue
+  g.res_range.resize(n_res);
+  int off = 0;
+  for (int i = 0; i < n_res; ++i) {
+    g.res_range[i] = make_int2(off, off + count[i]);
+    off += count[i];
+  }
+  std::vector<int> fill(n_res, 0);
+  g.res_xyz.resize(n);
+  for (int a = 0; a < n; ++a) {
+    const int i = residue[a];
+    g.res_xyz[g.res_range[i].x + fill[i]++] = make_float4(xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], 0.f);
+  }
+  // lattice over the receptor box grown by the cutoff and one cell
+  double lo[3], hi[3];
+  for (int c = 0; c < 3; ++c) {
+    lo[c] = hi[c] = xyz[c];
+    for (int a = 1; a < n; ++a) {
+      lo[c] = std::min(lo[c], double(xyz[3 * a + c]));
+      hi[c] = std::max(hi[c], double(xyz[3 * a + c]));
+    }
+    lo[c] -= kMdnCutoff + kMdnCell;
+    hi[c] += kMdnCutoff + kMdnCell;
+    g.origin[c] = float(lo[c]);
+    g.dims[c] = int(std::ceil((hi[c] - double(g.origin[c])) / kMdnCell));
+  }
+  const long long ncell = (long long)g.dims[0] * g.dims[1] * g.dims[2];
+  if (ncell > (1ll << 26)) {
+    err = "receptor too large for the E_MDN lattice";
+    return DOCK_E_LIMIT;
+  }
+  // residue i is listed in every cell whose box comes within the cutoff
+  // (plus 1e-3 A for rounding of the query's cell index) of one of its atoms
+  const double reach = kMdnCutoff + 1e-3;
+  std::vector<int> stamp(ncell, -1);
+  std::vector<std::vector<int>> lists(ncell);
+  for (int i = 0; i < n_res; ++i) {
+    for (int k = g.res_range[i].x; k < g.res_range[i].y; ++k) {
+      const float4 r = g.res_xyz[k];
+      const double p[3] = {r.x, r.y, r.z};
+      int c0[3], c1[3];
+      for (int c = 0; c < 3; ++c) {
+        c0[c] = std::max(0, int(std::floor((p[c] - reach - g.origin[c]) / kMdnCell)));
+        c1[c] = std::min(g.dims[c] - 1, int(std::floor((p[c] + reach - g.origin[c]) / kMdnCell)));
+      }
+      for (int z = c0[2]; z <= c1[2]; ++z)
+        for (int y = c0[1]; y <= c1[1]; ++y)
+          for (int x = c0[0]; x <= c1[0]; ++x) {
+            const long long cell = ((long long)z * g.dims[1] + y) * g.dims[0] + x;
+            if (stamp[cell] == i) continue;
+            const int idx[3] = {x, y, z};
+            double d2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+              const double b0 = g.origin[c] + double(idx[c]) * kMdnCell, b1 = b0 + kMdnCell;
+              const double dd = p[c] < b0 ? b0 - p[c] : (p[c] > b1 ? p[c] - b1 : 0.0);
+              d2 += dd * dd;
+            }
+            if (d2 < reach * reach) {
+              stamp[cell] = i;
+              lists[cell].push_back(i);
+            }
+          }
+    }
+  }
+  g.cell_start.resize(ncell + 1);
+  g.cell_start[0] = 0;
+  for (long long c = 0; c < ncell; ++c) g.cell_start[c + 1] = g.cell_start[c] + int(lists[c].size());
+  g.cell_res.reserve(g.cell_start[ncell]);
+  for (long long c = 0; c < ncell; ++c) g.cell_res.insert(g.cell_res.end(), lists[c].begin(), lists[c].end());
+  return DOCK_OK;
+}
+
+}  // namespace dock

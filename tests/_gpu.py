@@ -32,11 +32,11 @@ def lib():
     return D
 
 
-def load_pocket(pk, preset=P.PRESET_TRIDS, weights=None, keep=False, direct=False):
+def load_pocket(pk, preset=P.PRESET_TRIDS, weights=None, keep=False, direct=False, residue=None):
     D = lib()
     return D.dock_load_pocket(pk.xyz, pk.type, pk.origin, pk.spacing, pk.dims, preset=preset,
                               weights=weights, keep_per_term=keep,
-                              inter_mode=D.INTER_DIRECT if direct else D.INTER_GRID)
+                              inter_mode=D.INTER_DIRECT if direct else D.INTER_GRID, residue=residue)
 
 
 def load_ligands(L, host_only=False):

@@ -15,6 +15,7 @@ import pytest
 
 import synth
 from oracle import topology, maps as MAPS, score as SC, sampler as SM, params as P, philox as PX
+from oracle import fk as FK
 from tests import _gpu as G
 from tests._tiny import tiny_pocket, tiny_ligand
 
@@ -284,3 +285,67 @@ def test_sampler_direct_mode_runs_and_forms_agree(D):
     for k in ("q_cur", "E_cur", "q_best", "E_best"):
         assert torch.equal(a[k], b[k]), k
     assert bool(torch.all(b["E_best"] <= b["E_cur"]))
+
+
+def _mdn_case(D, pk, L, n_per, kinds, rng, tag, K=4):
+    """Score + gradient with the E_MDN term (supplied mixture parameters)
+    against the oracle's physics score plus its E_MDN."""
+    from oracle import mdn as MDN
+    residue = synth.make_residues(pk)
+    n_res = int(residue.max()) + 1
+    params = synth.make_mdn_params(int(L.atom_off[-1]), n_res, K, seed=11)
+    w = G.weights32(P.PRESET_TRIDS)
+    p = G.load_pocket(pk, P.PRESET_TRIDS, w, residue=residue)
+    H = G.load_ligands(L)
+    D.dock_ligands_set_mdn(H, params)
+    sc = SC.LazyScorer(pk, P.PRESET_TRIDS, weights=w.astype(np.float64))
+    topos = [topology.from_ligands(L, i) for i in range(L.n_ligands)]
+    checked = skipped = 0
+    worst = [0.0, 0.0]
+    for i, t in enumerate(topos):
+        Q = np.concatenate([G.poses_for(t, n_per, rng, k) for k in kinds])
+        qq = np.zeros((len(Q), H.q_stride), np.float32)
+        qq[:, :t.n_dof] = Q
+        lig = torch.full((len(Q),), i, dtype=torch.int32, device="cuda")
+        E, g, _ = D.dock_score_grad(p, H, lig, torch.tensor(qq, device="cuda"), want_xyz=True)
+        E, g = E.cpu().numpy(), g.cpu().numpy()
+        ref = sc.score(t, Q.astype(np.float64))
+        a0 = int(L.atom_off[i])
+        Em, gm, mE, m = MDN.mdn_energy(ref["x"], pk.xyz, residue, params[a0:a0 + t.n_atoms].astype(np.float64))
+        full = dict(E=ref["E"] + Em, dEdq=ref["dEdq"] + FK.dof_gradient(t, Q.astype(np.float64), ref["x"], gm),
+                    S_abs=ref["S_abs"] + np.abs(Em), margin=np.minimum(ref["margin"], m),
+                    margin_E=np.minimum(ref["margin_E"], mE))
+        assert np.any(np.abs(Em) > 1e-3), "the term should contribute"
+        c, s, we, wg = G.compare_eval(E, g, full, t.n_dof, "%s lig %d" % (tag, i))
+        checked += c
+        skipped += s
+        worst = [max(worst[0], we), max(worst[1], wg)]
+    G.say(tag, "checked", checked, "gradient margin-skipped", skipped, "worst E/tol %.3g g/tol %.3g" % tuple(worst))
+    assert skipped <= max(2, 0.06 * (checked + skipped))
+    return p, H
+
+
+def test_mdn_term_against_oracle(D):
+    pk, L, _ = synth.workload("C1")
+    _mdn_case(D, pk[0], L, 32, ("near", "uniform"), np.random.default_rng(21), "mdn/C1")
+
+
+def test_mdn_term_ragged_sizes(D):
+    spec = [(10, 0), (14, 9), (30, 12), (45, 15), (90, 12)]
+    L = synth.pack_ligands([synth.make_ligand(n, t, np.random.default_rng(40 + n)) for n, t in spec])
+    L.pocket_index = np.zeros(L.n_ligands, np.int32)
+    pk = synth.make_pocket(800, grid=48, seed=9)
+    _mdn_case(D, pk, L, 6, ("near", "uniform"), np.random.default_rng(22), "mdn/ragged")
+
+
+def test_mdn_term_in_the_sampler(D):
+    pk, L, _ = synth.workload("C1")
+    p, H = _mdn_case(D, pk[0], L, 4, ("near",), np.random.default_rng(23), "mdn/sampler-setup")
+    runs = [D.dock_sample(p, H, n_traj=16, n_steps=6, n_local=4, seed=3, form=f) for f in (D.FORM_PLAIN, D.FORM_BATCHED)]
+    a, b = (D.dock_run_state(r)["E_best"].cpu().numpy() for r in runs)
+    assert np.all(np.isfinite(a)) and np.array_equal(a, b)
+    # the term changes the sampled energies
+    p0 = G.load_pocket(pk[0], P.PRESET_TRIDS, G.weights32(P.PRESET_TRIDS))
+    r0 = D.dock_sample(p0, H, n_traj=16, n_steps=6, n_local=4, seed=3, form=D.FORM_BATCHED)
+    e0 = D.dock_run_state(r0)["E_best"].cpu().numpy()
+    assert not np.array_equal(a, e0)

@@ -106,3 +106,15 @@ def test_error_codes():
     assert D.dock_ligand_info(H, 0)["n_atoms"] == 2
     with pytest.raises(D.DockError):
         D.dock_ligand_info(H, 5)
+
+
+def test_residue_and_mixture_argument_errors():
+    # pocket residue indices must cover 0 .. n_res - 1 (checked before any
+    # device work); mixture parameters need a device-backed ligand handle
+    xyz = np.arange(12, dtype=np.float32).reshape(4, 3)
+    types = np.zeros(4, np.uint8)
+    for residue in ([0, 0, 2, 2], [0, -1, 1, 1]):
+        assert _code(lambda: D.dock_load_pocket(xyz, types, [0, 0, 0], 0.5, (4, 4, 4),
+                                                residue=np.array(residue, np.int32), stream=0)) == -1
+    H = _one([0, 0], [3, 3], xyz[:2], [(0, 1)], [0])
+    assert _code(lambda: D.dock_ligands_set_mdn(H, np.ones((2, 3, 2, 3), np.float32))) == -1
