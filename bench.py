@@ -135,6 +135,53 @@ def cpu_baseline(name, n_lig_total, T_sample=32, S_sample=8, n_sample=8):
 
 # ------------------------------------------------------------------ main
 
+def _event_ms(fn):
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    res = fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b), res
+
+
+def extras(D, pk, L, T, S, n_sub=32):
+    """Side measurements on the same pocket: the map build, the adjoint of
+    the map build, and the sampler on a 32-ligand subset (spread over the
+    size range) in the direct pair mode and with the E_MDN term.  Device
+    time from events on the current stream (the stream the calls use)."""
+    import torch
+    out = {}
+    ms, pocket = _event_ms(lambda: load_pocket(D, pk))
+    out["map_build_ms"] = round(ms, 3)
+    lam = torch.randn((8, 3) + tuple(pk.dims[::-1]), device="cuda")
+    dx = torch.zeros((len(pk.xyz), 3), device="cuda")
+    dth = torch.zeros(13, dtype=torch.float64, device="cuda")
+    D.dock_pocket_map_adjoint(pocket, lam, dx, dth)
+    ms, _ = _event_ms(lambda: D.dock_pocket_map_adjoint(pocket, lam, dx, dth))
+    out["map_adjoint_ms"] = round(ms, 3)
+    order = np.argsort(np.diff(L.atom_off), kind="stable")
+    sub = np.sort(order[np.linspace(0, len(order) - 1, n_sub).astype(int)])
+    Ls = L.subset(sub)
+    Hs = D.dock_load_ligands(Ls.atom_off, Ls.element, Ls.n_h, Ls.xyz, Ls.bond_off, Ls.bonds, Ls.rotatable,
+                             pocket_index=Ls.pocket_index)
+    evals = n_sub * T * (1 + S * (N_LOCAL + 1))
+    modes = {}
+    residue = synth.make_residues(pk)
+    n_res = int(residue.max()) + 1
+    p_grid = pocket
+    p_direct = D.dock_load_pocket(pk.xyz, pk.type, pk.origin, pk.spacing, pk.dims, inter_mode=D.INTER_DIRECT)
+    p_mdn = D.dock_load_pocket(pk.xyz, pk.type, pk.origin, pk.spacing, pk.dims, residue=residue)
+    for name, pp in (("grid", p_grid), ("direct", p_direct), ("grid+E_MDN", p_mdn)):
+        if name == "grid+E_MDN":
+            D.dock_ligands_set_mdn(Hs, synth.make_mdn_params(int(Ls.atom_off[-1]), n_res, 4, seed=5))
+        ms, run = _event_ms(lambda: D.dock_sample(pp, Hs, n_traj=T, n_steps=S, n_local=N_LOCAL, seed=1,
+                                                  form=D.FORM_BATCHED))
+        modes[name] = dict(ms=round(ms, 3), evals_per_s=round(evals / (ms * 1e-3), 1))
+    out["sampler_modes"] = dict(ligands=n_sub, n_traj=T, n_steps=S, n_res=n_res, mdn_gaussians=4, **modes)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +190,8 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-ligand form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the side measurements (map build and adjoint, direct and E_MDN modes)")
     ap.add_argument("--graph", type=int, default=0, help="replay sampler launches as a hipGraph")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -265,6 +314,9 @@ def main():
                             ligands_per_s=round(H.n / (plain_ms * 1e-3), 2))
         out["batched_vs_plain"] = round(plain_ms / ms_step, 3)
         print("plain form: %.1f ms per step" % plain_ms, file=sys.stderr, flush=True)
+    if not args.no_extras:
+        out["extras"] = extras(D, pk, L, T, S)
+        print("extras done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, H.n)
