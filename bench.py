@@ -274,7 +274,7 @@ def main():
     tot_ms = sum(np.mean(d["ms"]) for d in per_bucket.values())
     dom = max(per_bucket.values(), key=lambda d: np.mean(d["ms"]))
     achieved = dom["flop"] / (np.mean(dom["ms"]) * 1e-3) / 1e12
-    traffic = measured_traffic("%d,%d,%d,false" % (dom["lanes"], dom["apl"], dom["block"]))
+    traffic = measured_traffic("%d,%d,%d,0" % (dom["lanes"], dom["apl"], dom["block"]))
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP32_TFLOPS, 4),
                     traffic=None if traffic is None else round(traffic),
