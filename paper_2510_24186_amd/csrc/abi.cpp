@@ -560,6 +560,7 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
       PairRec pr{};
       if (i0 < 0) {
         pr.w = kPairEmpty;
+        pr.rsum = kEmptyRsum;
         return pr;
       }
       const int ti = H.type[H.dfs_atom[i0]], tj = H.type[H.dfs_atom[j0]];
@@ -569,16 +570,31 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
       pr.rsum = tp.rsum;
       return pr;
     };
+    auto bits = [](float f) {
+      uint32_t u;
+      std::memcpy(&u, &f, 4);
+      return u;
+    };
     const LaneCfg lc = lane_cfg(g, 0);
     if (lc.apl == 1 && !pi_new.empty()) {
       const PassPlan plan = schedule_passes(H.n_atoms, pi_new, pj_new, lc.lpp);
       g.n_pass = plan.n_pass;
       g.pass_w = lc.lpp;
       g.pull_cap = plan.cap;
-      // slot record and the pull word of atom `slot` side by side: one
-      // 16-byte load per lane and pass
+      // 16-byte slot records (pair word, radius sum, d_clash^2 as the device
+      // squares it, log2 d_clash), then one pull word per slot
       for (size_t s = 0; s < plan.slot_i.size(); ++s) {
-        pairs.push_back(record(plan.slot_i[s], plan.slot_j[s]));
+        const int i0 = plan.slot_i[s], j0 = plan.slot_j[s];
+        pairs.push_back(record(i0, j0));
+        PairRec cl{};
+        if (i0 >= 0) {
+          const TypePair& tp = tab[H.type[H.dfs_atom[i0]] * kTypes + H.type[H.dfs_atom[j0]]];
+          cl.w = bits(tp.dclash2);
+          cl.rsum = float(std::log2(double(tp.dclash)));
+        }
+        pairs.push_back(cl);
+      }
+      for (size_t s = 0; s < plan.slot_i.size(); ++s) {
         PairRec pw;
         pw.w = uint32_t(plan.pulls[s]);
         const uint32_t hi = uint32_t(plan.pulls[s] >> 32);

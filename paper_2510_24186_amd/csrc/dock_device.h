@@ -94,14 +94,23 @@ DK_INLINE float dpp(float v) {
 // Sum over the group.  Every step adds a lane's value to its partner's, and
 // the partner does the same with the operands swapped, so all lanes end with
 // bitwise-identical sums (MC decisions taken from them are uniform).
+// Rows (16 lanes) and wave halves are exchanged with the gfx950 permlane
+// swaps: with both operands v, the two results hold v and its partner's
+// value in opposite order, so their sum is the butterfly step.
 template <int W>
 DK_INLINE float group_sum(float v) {
   v += dpp<kDppQuadXor1>(v);
   v += dpp<kDppQuadXor2>(v);
   v += dpp<kDppRowHalfMirror>(v);
   v += dpp<kDppRowMirror>(v);
-  if (W >= 32) v += __shfl_xor(v, 16, W);
-  if (W >= 64) v += __shfl_xor(v, 32, W);
+  if (W >= 32) {
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  }
+  if (W >= 64) {
+    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  }
   return v;
 }
 
@@ -121,14 +130,46 @@ DK_INLINE float group_scan(float v) {
 // ------------------------------------------------------------------ terms
 // Pair word: i | j << 8 | type_i << 16 | type_j << 20 | flags << 24, plus the
 // radius sum as a float.  flags bit0 donor/acceptor pair, bit1 both
-// hydrophobic, bit7 empty slot (no pair).  In the pass layout each slot
-// record is followed by an 8-byte pull word (the pull list of atom `slot` for
-// the pass, see PassPlan), so record p sits at entry 2p.
+// hydrophobic, bit7 empty slot (no pair).
+// Pass layout (one atom per lane): each slot takes two entries, the pair word
+// and radius sum, then the E_clash constants d_clash^2 and log2(d_clash)
+// (FP32 bit patterns in a second PairRec), so record p still starts at entry
+// 2p; after the n_prec slots come the pull words, one 8-byte entry per slot
+// (the pull list of atom `slot` for the pass, see PassPlan).  An empty slot
+// names atoms 0 and 0 with a radius sum of -1e4 and zero clash constants,
+// which makes every term of both presets exactly zero.
 constexpr uint32_t kPairEmpty = 0x80u << 24;
+constexpr float kEmptyRsum = -1.0e4f;
 struct PairRec {
   uint32_t w;
   float rsum;
 };
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// LDS byte addresses.  A gather address is formed in one instruction by a
+// byte dot product (v_dot4_u32_u8): byte k of a packed word times 16 plus the
+// array's base address.
+DK_INLINE uint32_t lds_addr(const void* p) {
+  return uint32_t(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) char*)p));
+}
+DK_INLINE uint32_t lds_entry16_k(uint32_t packed, int k, uint32_t base) {
+  return __builtin_amdgcn_udot4(packed, 16u << (8 * k), base, false);
+}
+template <int K>
+DK_INLINE uint32_t lds_entry16(uint32_t packed, uint32_t base) {
+  return lds_entry16_k(packed, K, base);
+}
+// 16-byte entries are read and written whole: on gfx950 a 12-byte LDS access
+// costs about twice a 16-byte one (the volatile read keeps the compiler from
+// narrowing it when the fourth word is unused).
+DK_INLINE f32x4_t lds_read4(uint32_t a) {
+  return *(const volatile __attribute__((address_space(3))) f32x4_t*)(uintptr_t)a;
+}
+DK_INLINE void lds_write4(uint32_t a, float x, float y, float z) {
+  const f32x4_t v = {x, y, z, 0.f};
+  *(__attribute__((address_space(3))) f32x4_t*)(uintptr_t)a = v;
+}
 
 // Loads through a pointer known to address global memory.  Pointers read
 // out of device-side structs (the pocket table) are generic to the
@@ -138,7 +179,6 @@ template <typename T>
 DK_INLINE T ldg(const T* p) {
   return *(const __attribute__((address_space(1))) T*)p;
 }
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
 DK_INLINE float4 ldg(const float4* p) {
   const f32x4_t v = *(const __attribute__((address_space(1))) f32x4_t*)p;
@@ -164,6 +204,7 @@ constexpr float kLn2 = 0.6931471805599453f;
 // normal positive arguments: the clash term only sees d in [0.1, d_clash).
 DK_INLINE float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
 DK_INLINE float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
+DK_INLINE float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Weighted TRIDS terms (Methods: E_long, E_clash, E_Hbond) at distance d
 // (d2 = d*d): energy and dE/dd.
@@ -189,6 +230,30 @@ DK_INLINE void trids_pair(float d2, float d, float rsum, uint32_t flags, const f
     const float ex = exp2_hw(t * t * (-kLog2e / 0.18f));
     e -= w[2] * ex;
     de += w[2] * ex * t * (2.0f / 0.18f);
+  }
+}
+
+// The TRIDS terms as trids_pair, with the clash cutoff and log2 of the clash
+// distance taken from the slot record (dc2 = d_clash^2, l2dc = log2 d_clash):
+// -log(dd / dc) = -ln2 (log2 dd - log2 dc), and for d > 0.1 the derivative
+// -1/d comes from the caller's 1/d.
+DK_INLINE void trids_pair_k(float d2, float d, float inv_d, float rsum, float dc2, float l2dc,
+                            uint32_t flags, const float* w, float& e, float& de) {
+  const float s = d - rsum - 3.0f;
+  float ex = exp2_hw(s * s * (-0.25f * kLog2e));
+  ex = d2 < 100.0f ? ex : 0.f;
+  e = -w[0] * ex;
+  de = (w[0] * 0.5f) * s * ex;
+  if (d2 < dc2) {
+    const bool far = d > 0.1f;
+    e -= (w[1] * kLn2) * (log2_hw(far ? d : 0.1f) - l2dc);
+    if (far) de -= w[1] * inv_d;
+  }
+  if ((flags & 1u) && d2 < 3.4f * 3.4f) {
+    const float t = d - 2.88f;
+    const float eh = exp2_hw(t * t * (-kLog2e / 0.18f));
+    e -= w[2] * eh;
+    de += (w[2] * (2.0f / 0.18f)) * t * eh;
   }
 }
 
@@ -328,10 +393,10 @@ struct Trilerp {
 
 DK_INLINE void cell_axis(float p, float o, float hi, float inv_h, int n, float& pc, bool& in, int& c,
                          float& f) {
-  pc = fminf(fmaxf(p, o), hi);
-  in = (p >= o) && (p <= hi);
-  const float u = (pc - o) * inv_h;
-  c = min(max(int(floorf(u)), 0), n - 2);
+  pc = __builtin_amdgcn_fmed3f(p, o, hi);  // clamp to [o, hi]
+  in = pc == p;
+  const float u = (pc - o) * inv_h;        // >= 0, so truncation is floor
+  c = min(int(u), n - 2);
   f = u - float(c);
 }
 
@@ -343,9 +408,10 @@ DK_INLINE Trilerp trilerp(const float* __restrict__ M, const GridDev& g, float p
   cell_axis(px, g.origin[0], g.hi[0], g.inv_spacing, g.dims[0], pcx, ix, cx, t.fx);
   cell_axis(py, g.origin[1], g.hi[1], g.inv_spacing, g.dims[1], pcy, iy, cy, t.fy);
   cell_axis(pz, g.origin[2], g.hi[2], g.inv_spacing, g.dims[2], pcz, iz, cz, t.fz);
-  const int nx = g.dims[0], nxy = g.dims[0] * g.dims[1];
-  t.base = (cz * g.dims[1] + cy) * nx + cx;
-  const float* p0 = M + t.base;
+  // nodes per map <= 2^30: 32-bit node indices
+  const uint32_t nx = uint32_t(g.dims[0]), nxy = uint32_t(g.dims[0]) * uint32_t(g.dims[1]);
+  t.base = int((uint32_t(cz) * uint32_t(g.dims[1]) + uint32_t(cy)) * nx + uint32_t(cx));
+  const float* p0 = M + uint32_t(t.base);
   const float c000 = ldg(p0), c100 = ldg(p0 + 1), c010 = ldg(p0 + nx), c110 = ldg(p0 + nx + 1);
   const float c001 = ldg(p0 + nxy), c101 = ldg(p0 + nxy + 1), c011 = ldg(p0 + nxy + nx),
               c111 = ldg(p0 + nxy + nx + 1);
@@ -360,14 +426,13 @@ DK_INLINE Trilerp trilerp(const float* __restrict__ M, const GridDev& g, float p
   const float gxf = dxy0 + fz * (dxy1 - dxy0);
   const float gyf = (x10 - x00) + fz * ((x11 - x01) - (x10 - x00));
   const float gzf = y1 - y0;
-  t.gx = ix ? gxf * g.inv_spacing : 0.f;
-  t.gy = iy ? gyf * g.inv_spacing : 0.f;
-  t.gz = iz ? gzf * g.inv_spacing : 0.f;
+  // outside the box along an axis the map gradient is zero there and the
+  // penalty's slope is +-10 (the offset is nonzero exactly when outside)
   const float ox = px - pcx, oy = py - pcy, oz = pz - pcz;
   t.eout = kOutK * (fabsf(ox) + fabsf(oy) + fabsf(oz));
-  t.gx += ox > 0.f ? kOutK : (ox < 0.f ? -kOutK : 0.f);
-  t.gy += oy > 0.f ? kOutK : (oy < 0.f ? -kOutK : 0.f);
-  t.gz += oz > 0.f ? kOutK : (oz < 0.f ? -kOutK : 0.f);
+  t.gx = ix ? gxf * g.inv_spacing : copysignf(kOutK, ox);
+  t.gy = iy ? gyf * g.inv_spacing : copysignf(kOutK, oy);
+  t.gz = iz ? gzf * g.inv_spacing : copysignf(kOutK, oz);
   return t;
 }
 
@@ -798,7 +863,7 @@ DK_INLINE float chain_rule(const LaneLig<APL>& L, const Rigid& rg, const float (
     // axis atoms of this lane's torsion
     const float4 xa = S.xs[L.ta], xb = S.xs[L.tb];
     float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
-    const float inv = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+    const float inv = __builtin_amdgcn_rsqf(ux * ux + uy * uy + uz * uz);
     ux *= inv; uy *= inv; uz *= inv;
     const float bx = xb.x - Tx, by = xb.y - Ty, bz = xb.z - Tz;
     // sum_sub (x_i - x_b) x g_i = St - r_b x Sg
@@ -826,6 +891,28 @@ DK_INLINE float pair_force(const LaneLig<APL>& L, const PairRec& pr, const float
     trids_pair(d2, d, pr.rsum, flags, L.w, e, de);
   else
     vina_pair(d2, d, pr.rsum, flags, L.w, e, de);
+  const float c = de * inv_d;
+  f[0] = c * dx;
+  f[1] = c * dy;
+  f[2] = c * dz;
+  return e;
+}
+
+// pair_force for a pass-layout slot: coordinates as read from the slab, the
+// clash constants from the slot's second entry.
+template <int APL>
+DK_INLINE float pair_force_slot(const LaneLig<APL>& L, const uint4& rp, const f32x4_t& xi, const f32x4_t& xj,
+                                float (&f)[3]) {
+  const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+  const float d2 = dx * dx + dy * dy + dz * dz;
+  const float inv_d = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
+  const float d = d2 * inv_d;
+  const float rsum = __uint_as_float(rp.y);
+  float e, de;
+  if (L.preset == DOCK_PRESET_TRIDS)
+    trids_pair_k(d2, d, inv_d, rsum, __uint_as_float(rp.z), __uint_as_float(rp.w), rp.x >> 24, L.w, e, de);
+  else
+    vina_pair(d2, d, rsum, rp.x >> 24, L.w, e, de);
   const float c = de * inv_d;
   f[0] = c * dx;
   f[1] = c * dy;
@@ -880,39 +967,46 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
 #pragma unroll
   for (int s = 0; s < APL; ++s) fsum[s][0] = fsum[s][1] = fsum[s][2] = 0.f;
   if (APL == 1 && L.n_pass > 0) {
-    // ---- pass layout: lane r evaluates slot r of every pass, stores the
-    // pair force in its slot, then gathers the slots listed for its atom
+    // ---- pass layout: lane r evaluates slot r of every pass and stores +f
+    // and -f of its pair in force entries r and W + r; then every atom lane
+    // sums the 4 (or 8) entries its pull word names (unused bytes name the
+    // zero entry 2W).  Plain stores and a fixed summation order: the result
+    // does not depend on timing.
     const int W = L.pass_w;
+    const bool slot_lane = r < W;
     const uint4* recs = reinterpret_cast<const uint4*>(pairs);
-    const uint32_t none = uint32_t(2 * W) * 0x01010101u;
+    const uint2* pulls = reinterpret_cast<const uint2*>(pairs + 2 * L.n_prec);
+    const uint32_t xs_a = lds_addr(S.xs), fb_a = lds_addr(S.fb);
     if (r == 0) S.fb[2 * W] = make_float4(0.f, 0.f, 0.f, 0.f);
+    // the next pass's record and pull word are read before this pass's
+    // gather, so their latency overlaps the gather and the sums
+    const int lane_slot = slot_lane ? r : 0;
+    uint4 rp_next = recs[lane_slot];
+    // lanes without a slot hold no atom either: their gather is unused
+    uint2 pw_next = pulls[lane_slot];
     for (int ps = 0; ps < L.n_pass; ++ps) {
-      const int slot = r < W ? ps * W + r : ps * W;
-      const uint4 rp = recs[slot];
-      PairRec pr;
-      pr.w = rp.x;
-      pr.rsum = __uint_as_float(rp.y);
-      uint2 pw = make_uint2(rp.z, rp.w);
-      float f[3] = {0.f, 0.f, 0.f};
-      if (r < W && !(pr.w & kPairEmpty)) {
-        const int i = pr.w & 0xff, j = (pr.w >> 8) & 0xff;
-        e_lane += pair_force(L, pr, S.xs[i], S.xs[j], f);
+      const uint4 rp = rp_next;
+      const uint2 pw = pw_next;
+      const f32x4_t xi = lds_read4(lds_entry16<0>(rp.x, xs_a));
+      const f32x4_t xj = lds_read4(lds_entry16<1>(rp.x, xs_a));
+      float f[3];
+      const float e = pair_force_slot(L, rp, xi, xj, f);
+      if (slot_lane) {
+        e_lane += e;
+        lds_write4(fb_a + 16u * uint32_t(r), f[0], f[1], f[2]);
+        lds_write4(fb_a + 16u * uint32_t(W + r), -f[0], -f[1], -f[2]);
       }
-      if (r < W) {
-        S.fb[r] = make_float4(f[0], f[1], f[2], 0.f);
-        S.fb[W + r] = make_float4(-f[0], -f[1], -f[2], 0.f);
-      } else {
-        pw = make_uint2(none, none);
-      }
+      const int next = (ps + 1 < L.n_pass ? ps + 1 : ps) * W + lane_slot;
+      rp_next = recs[next];
+      pw_next = pulls[next];
       wave_sync();
-      // 4 or 8 entries, all read before any is summed (unused ones name the
-      // zero entry)
-      float4 v[kMaxPull];
+      // every entry is read before any is summed
+      f32x4_t v[kMaxPull];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] = S.fb[(pw.x >> (8 * c)) & 0xffu];
+      for (int c = 0; c < 4; ++c) v[c] = lds_read4(lds_entry16_k(pw.x, c, fb_a));
       if (L.pull_cap > 4) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) v[4 + c] = S.fb[(pw.y >> (8 * c)) & 0xffu];
+        for (int c = 4; c < 8; ++c) v[c] = lds_read4(lds_entry16_k(pw.y, c & 3, fb_a));
 #pragma unroll
         for (int c = 4; c < 8; ++c) {
           fsum[0][0] += v[c].x;

@@ -486,23 +486,25 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const Pocket
         E = o.E;
         if (t == a.n_local) break;
         const float g = o.g;
+        // square roots and quotients on the hardware units (about 1 ulp;
+        // the IEEE-exact sequences cost ~12 instructions each)
         float step;
         if (a.local_opt == DOCK_LOCAL_SGD) {
           step = a.lr * g;
         } else if (a.local_opt == DOCK_LOCAL_RMSPROP) {
           v = a.rms_alpha * v + (1.f - a.rms_alpha) * g * g;
-          step = a.lr * g / (sqrtf(v) + a.eps);
+          step = a.lr * g * rcp_hw(sqrt_hw(v) + a.eps);
         } else if (a.local_opt == DOCK_LOCAL_ADAGRAD) {
           v += g * g;
-          step = a.lr * g / (sqrtf(v) + a.eps);
+          step = a.lr * g * rcp_hw(sqrt_hw(v) + a.eps);
         } else {
           if (a.local_opt == DOCK_LOCAL_ADAMW) qn *= 1.f - a.lr * a.weight_decay;
           m = a.b1 * m + (1.f - a.b1) * g;
           v = a.b2 * v + (1.f - a.b2) * g * g;
           b1t *= a.b1;
           b2t *= a.b2;
-          const float mh = m / (1.f - b1t), vh = v / (1.f - b2t);
-          step = a.lr * mh / (sqrtf(vh) + a.eps);
+          const float mh = m * rcp_hw(1.f - b1t), vh = v * rcp_hw(1.f - b2t);
+          step = a.lr * mh * rcp_hw(sqrt_hw(vh) + a.eps);
         }
         if (dof) qn = wrap_clamp(qn - step, r, L);
       }

@@ -287,37 +287,97 @@ namespace dock {
 
 namespace {
 
-// Greedy fill of passes with at most `cap` incidences per atom and pass.
-void fill_passes(int n_atoms, const std::vector<int>& pi, const std::vector<int>& pj, int width, int cap,
-                 const std::vector<int>& order, PassPlan& plan) {
+// Assigns every pair to one of k passes of at most `width` pairs, with at
+// most `cap` pairs per atom and pass.  Pairs of busy atoms go first, each to
+// the pass where its two atoms have the fewest pairs so far (then the
+// emptiest pass).  A pair that fits nowhere takes the place of a pair that
+// blocks it in some pass, which moves to a pass with room for it.  Returns
+// false when that also fails (the caller then tries k + 1).
+bool assign_passes(int n_atoms, const std::vector<int>& pi, const std::vector<int>& pj, int width, int cap,
+                   int k, const std::vector<int>& order, std::vector<int>& pass_of) {
   const size_t P = pi.size();
-  plan = PassPlan();
-  plan.cap = cap;
-  std::vector<char> used(P, 0);
-  std::vector<int> cnt(n_atoms);
-  size_t placed = 0, first_free = 0;
-  while (placed < P) {
-    std::fill(cnt.begin(), cnt.end(), 0);
-    const size_t base = plan.slot_i.size();
-    plan.slot_i.resize(base + width, -1);
-    plan.slot_j.resize(base + width, -1);
-    int fill = 0;
-    while (first_free < P && used[order[first_free]]) ++first_free;
-    for (size_t k = first_free; k < P && fill < width; ++k) {
-      const int p = order[k];
-      if (used[p]) continue;
-      const int a = pi[p], b = pj[p];
-      if (cnt[a] >= cap || cnt[b] >= cap) continue;
-      ++cnt[a];
-      ++cnt[b];
-      used[p] = 1;
-      plan.slot_i[base + fill] = a;
-      plan.slot_j[base + fill] = b;
-      ++fill;
-      ++placed;
+  std::vector<int> load(size_t(n_atoms) * k, 0), size(k, 0);
+  std::vector<std::vector<int>> members(k);
+  pass_of.assign(P, -1);
+  auto L = [&](int a, int p) -> int& { return load[size_t(a) * k + p]; };
+  auto fits = [&](int e, int p) { return size[p] < width && L(pi[e], p) < cap && L(pj[e], p) < cap; };
+  auto place = [&](int e, int p) {
+    pass_of[e] = p;
+    ++L(pi[e], p);
+    ++L(pj[e], p);
+    ++size[p];
+    members[p].push_back(e);
+  };
+  auto unplace = [&](int e) {
+    const int p = pass_of[e];
+    pass_of[e] = -1;
+    --L(pi[e], p);
+    --L(pj[e], p);
+    --size[p];
+    members[p].erase(std::find(members[p].begin(), members[p].end(), e));
+  };
+  for (int e : order) {
+    const int a = pi[e], b = pj[e];
+    int best = -1;
+    long best_score = 0;
+    for (int p = 0; p < k; ++p) {
+      if (!fits(e, p)) continue;
+      const long score = long(L(a, p) + L(b, p)) * (width + 1) + size[p];
+      if (best < 0 || score < best_score) {
+        best = p;
+        best_score = score;
+      }
     }
-    ++plan.n_pass;
+    if (best >= 0) {
+      place(e, best);
+      continue;
+    }
+    bool done = false;
+    for (int p = 0; p < k && !done; ++p) {
+      const bool full = size[p] >= width, a_full = L(a, p) >= cap, b_full = L(b, p) >= cap;
+      if (a_full && b_full) continue;
+      const int blocker = a_full ? a : (b_full ? b : -1);
+      const std::vector<int> cand = members[p];
+      for (int f : cand) {
+        if (blocker >= 0 && pi[f] != blocker && pj[f] != blocker) continue;
+        if (blocker < 0 && !full) continue;
+        int q = 0;
+        while (q < k && (q == p || !fits(f, q))) ++q;
+        if (q == k) continue;
+        unplace(f);
+        place(f, q);
+        place(e, p);
+        done = true;
+        break;
+      }
+    }
+    if (!done) return false;
   }
+  return true;
+}
+
+// The plan with the fewest passes that the assignment finds for one cap,
+// starting from the lower bound max(P / width, max degree / cap).
+PassPlan plan_for_cap(int n_atoms, const std::vector<int>& pi, const std::vector<int>& pj, int width, int cap,
+                      const std::vector<int>& order, int max_deg) {
+  const int P = int(pi.size());
+  int k = std::max((P + width - 1) / width, (max_deg + cap - 1) / cap);
+  std::vector<int> pass_of;
+  // k = P always succeeds (every pair can have a pass of its own)
+  while (!assign_passes(n_atoms, pi, pj, width, cap, k, order, pass_of)) ++k;
+  PassPlan plan;
+  plan.n_pass = k;
+  plan.cap = cap;
+  plan.slot_i.assign(size_t(k) * width, -1);
+  plan.slot_j.assign(size_t(k) * width, -1);
+  std::vector<int> fill(k, 0);
+  for (int e = 0; e < P; ++e) {
+    const int p = pass_of[e];
+    const size_t slot = size_t(p) * width + fill[p]++;
+    plan.slot_i[slot] = pi[e];
+    plan.slot_j[slot] = pj[e];
+  }
+  return plan;
 }
 
 }  // namespace
@@ -332,26 +392,22 @@ PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vec
     ++deg[pj[p]];
   }
   const int max_deg = *std::max_element(deg.begin(), deg.end());
-  const int passes0 = int((P + width - 1) / width);
-  // pairs touching busy atoms first, so that hubs spread over every pass
+  // pairs of busy atoms first (larger endpoint degree, then the smaller one)
   std::vector<int> order(P);
   for (size_t p = 0; p < P; ++p) order[p] = int(p);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return std::max(deg[pi[a]], deg[pj[a]]) > std::max(deg[pi[b]], deg[pj[b]]);
-  });
-  // incidences one atom may take per pass: enough for a full pass on
-  // average (2 * width / n_atoms) and for the busiest atom to finish within
-  // the minimal pass count, plus one of slack.  The gather reads 4 or 8
-  // entries per pass, so a cap of 4 is also tried and the cheaper plan kept
-  // (cost ~ passes * (pair work + gather work)).
-  int cap = std::max((2 * width + n_atoms - 1) / n_atoms, (max_deg + passes0 - 1) / passes0) + 1;
-  cap = std::min(cap, kMaxPull);
-  fill_passes(n_atoms, pi, pj, width, cap, order, plan);
-  if (cap > 4) {
-    PassPlan p4;
-    fill_passes(n_atoms, pi, pj, width, 4, order, p4);
-    const auto cost = [](const PassPlan& q) { return double(q.n_pass) * (100.0 + 5.0 * (q.cap <= 4 ? 4 : 8)); };
-    if (cost(p4) <= cost(plan)) plan = std::move(p4);
+  const auto key = [&](int e) {
+    const int hi = std::max(deg[pi[e]], deg[pj[e]]), lo = std::min(deg[pi[e]], deg[pj[e]]);
+    return long(hi) * (n_atoms + 1) + lo;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) > key(b); });
+  // The gather reads 4 or 8 entries per pass.  Cost of a plan ~ passes x
+  // (pair work, about 12 gathered entries' worth, + entries read); the cap-8
+  // plan is kept only when it is cheaper.
+  plan = plan_for_cap(n_atoms, pi, pj, width, 4, order, max_deg);
+  if ((max_deg + 3) / 4 > (int(P) + width - 1) / width) {
+    PassPlan p8 = plan_for_cap(n_atoms, pi, pj, width, kMaxPull, order, max_deg);
+    const auto cost = [](const PassPlan& q) { return q.n_pass * (12 + (q.cap <= 4 ? 4 : 8)); };
+    if (cost(p8) < cost(plan)) plan = std::move(p8);
   }
   // pull lists: per pass and atom, the force entries of its pairs (slot s
   // for the first endpoint, width + s for the second); unused bytes name the
