@@ -955,6 +955,12 @@ struct dock_run_s {
   std::vector<hipEvent_t> event_pool;
   size_t events_used = 0;
   bool recording = false;
+  // batched form with several buckets: bucket b > 0 runs on side[b - 1],
+  // forked from and joined back into the caller's stream, so a bucket too
+  // small to fill the chip and the tail of a large one overlap
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
 };
 
 static hipEvent_t pool_event(dock_run_s* r) {
@@ -997,6 +1003,9 @@ static hipError_t timed_launch(dock_run_s* r, const SampleArgs& a, int bucket, i
 
 static void free_run(dock_run_s* r) {
   for (hipEvent_t e : r->event_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : r->join) (void)hipEventDestroy(e);
+  for (hipStream_t q : r->side) (void)hipStreamDestroy(q);
+  if (r->fork) (void)hipEventDestroy(r->fork);
   if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
   if (r->graph) (void)hipGraphDestroy(r->graph);
   if (r->ev0) (void)hipEventDestroy(r->ev0);
@@ -1046,11 +1055,17 @@ static hipError_t enqueue_phase(dock_run_s* r, bool init, int steps, hipStream_t
                                                           : r->p.steps_per_launch;
   const int n_chunks = init ? 1 : (steps + chunk - 1) / chunk;
   hipError_t e = hipSuccess;
+  const bool fork = r->p.form == DOCK_FORM_BATCHED && !r->side.empty();
   if (r->p.form == DOCK_FORM_BATCHED) {
     const int need = n_chunks * int(r->buckets.size());
     if (need > r->n_queue) return hipErrorInvalidValue;
     e = launch_fill_int(r->d_queue, need, 0, s);
     if (e != hipSuccess) return e;
+  }
+  if (fork) {
+    if ((e = hipEventRecord(r->fork, s)) != hipSuccess) return e;
+    for (hipStream_t q : r->side)
+      if ((e = hipStreamWaitEvent(q, r->fork, 0)) != hipSuccess) return e;
   }
   for (int c = 0; c < n_chunks; ++c) {
     SampleArgs a = base_args(r);
@@ -1064,7 +1079,8 @@ static hipError_t enqueue_phase(dock_run_s* r, bool init, int steps, hipStream_t
         a.n_items = B.n_items;
         a.queue = r->d_queue + c * int(r->buckets.size()) + int(b);
         a.max_pairs = B.max_pairs;
-        e = timed_launch(r, a, int(b), B.lpp, B.apl, B.grid, B.block, s);
+        const hipStream_t bs = (fork && b > 0) ? r->side[b - 1] : s;
+        e = timed_launch(r, a, int(b), B.lpp, B.apl, B.grid, B.block, bs);
         if (e != hipSuccess) return e;
       }
     } else {
@@ -1079,6 +1095,11 @@ static hipError_t enqueue_phase(dock_run_s* r, bool init, int steps, hipStream_t
       }
     }
   }
+  if (fork)
+    for (size_t k = 0; k < r->side.size(); ++k) {
+      if ((e = hipEventRecord(r->join[k], r->side[k])) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(s, r->join[k], 0)) != hipSuccess) return e;
+    }
   if (!init) e = launch_add_int(r->d_step, steps, s);
   return e;
 }
@@ -1235,12 +1256,14 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   } else {
     for (Bucket& B : r->buckets) {
       const int gpb = B.block / B.lpp;
-      // longest work first: cost ~ pairs + 4 * atoms per evaluation
+      // longest work first: cost ~ pair slots (empty ones included) + 4 * atoms
+      // per evaluation
       std::vector<int> ligs = B.ligs;
-      std::stable_sort(ligs.begin(), ligs.end(), [&](int x, int y) {
-        const LigDev &gx = L->h_ligs[x], &gy = L->h_ligs[y];
-        return gx.n_pairs + 4 * gx.n_atoms > gy.n_pairs + 4 * gy.n_atoms;
-      });
+      const auto cost = [&](int l) {
+        const LigDev& g = L->h_ligs[l];
+        return (g.n_pass > 0 ? g.n_prec : g.n_pairs) + 4 * g.n_atoms;
+      };
+      std::stable_sort(ligs.begin(), ligs.end(), [&](int x, int y) { return cost(x) > cost(y); });
       B.item_off = int(items.size());
       for (int l : ligs) {
         if (ov && ov->subset && !(*ov->subset)[l]) continue;
@@ -1256,6 +1279,18 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   for (const Bucket& B : r->buckets)
     if (sample_lds_bytes(B.lpp, B.apl, B.block, B.max_pairs) > 64 * 1024)
       return bail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
+  if (p->form == DOCK_FORM_BATCHED && r->buckets.size() > 1) {
+    hipError_t se = hipEventCreateWithFlags(&r->fork, hipEventDisableTiming);
+    for (size_t b = 1; b < r->buckets.size() && se == hipSuccess; ++b) {
+      hipStream_t q = nullptr;
+      hipEvent_t j = nullptr;
+      se = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
+      if (se == hipSuccess) r->side.push_back(q);
+      if (se == hipSuccess) se = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+      if (se == hipSuccess) r->join.push_back(j);
+    }
+    if (se != hipSuccess) return bail(DOCK_E_HIP, std::string("bucket streams: ") + hipGetErrorString(se));
+  }
   // ---- buffers
   const size_t nt = size_t(r->n_lig) * r->T;
   const int chunk = p->steps_per_launch > 0 ? p->steps_per_launch : std::max(1, p->n_steps);
