@@ -270,9 +270,9 @@ def main():
                                               items=int(l["n_items"]), ms=[], flop=flop,
                                               ligands=int(np.sum(lb == b))))
             d["ms"].append(l["ms"])
-    tot_flop = sum(d["flop"] for d in per_bucket.values())
-    tot_ms = sum(np.mean(d["ms"]) for d in per_bucket.values())
-    dom = max(per_bucket.values(), key=lambda d: np.mean(d["ms"]))
+    # lane buckets run concurrently (side streams): the dominant kernel is
+    # the one with the most work, its duration as measured while overlapped
+    dom = max(per_bucket.values(), key=lambda d: d["flop"])
     achieved = dom["flop"] / (np.mean(dom["ms"]) * 1e-3) / 1e12
     traffic = measured_traffic("%d,%d,%d,0" % (dom["lanes"], dom["apl"], dom["block"]))
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
@@ -281,7 +281,7 @@ def main():
                     frac_of_packed_peak=round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
                     kernel="sample_kernel<%d,%d,%d>" % (dom["lanes"], dom["apl"], dom["block"]),
                     launch_ms=round(float(np.mean(dom["ms"])), 3),
-                    all_launches_tflops=round(tot_flop / (tot_ms * 1e-3) / 1e12, 3),
+                    sampler_tflops=round(float(np.sum(flops_lig)) / (float(np.mean(kern_ms)) * 1e-3) / 1e12, 3),
                     buckets=[dict(lanes=d["lanes"], atoms_per_lane=d["apl"], ligands=d["ligands"],
                                   block=d["block"], grid=d["grid"], work_items=d["items"],
                                   ms=round(float(np.mean(d["ms"])), 3),
