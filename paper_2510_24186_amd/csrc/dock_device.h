@@ -90,6 +90,19 @@ template <int CTRL, int ROW_MASK = 0xf>
 DK_INLINE float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
 }
+// v += (last lane of the previous row) in rows 1 and 3, and v += lane 31 in
+// rows 2 and 3: one DPP add each, the disabled rows keeping v.  (Written out
+// because the compiler emits a move, an add and a reset of the move's old
+// value for the masked form; s_nop 1 gives the two wait states a DPP read
+// needs after a VALU write of its source.)
+DK_INLINE float add_row_bcast15(float v) {
+  asm("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf" : "+v"(v));
+  return v;
+}
+DK_INLINE float add_row_bcast31(float v) {
+  asm("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf" : "+v"(v));
+  return v;
+}
 
 // Sum over the group.  Every step adds a lane's value to its partner's, and
 // the partner does the same with the operands swapped, so all lanes end with
@@ -122,8 +135,8 @@ DK_INLINE float group_scan(float v) {
   v += dpp<kDppRowShr2>(v);
   v += dpp<kDppRowShr4>(v);
   v += dpp<kDppRowShr8>(v);
-  if (W >= 32) v += dpp<kDppRowBcast15, 0xa>(v);
-  if (W >= 64) v += dpp<kDppRowBcast31, 0xc>(v);
+  if (W >= 32) v = add_row_bcast15(v);
+  if (W >= 64) v = add_row_bcast31(v);
   return v;
 }
 
@@ -249,9 +262,12 @@ DK_INLINE void trids_pair_k(float d2, float d, float inv_d, float rsum, float dc
     e -= (w[1] * kLn2) * (log2_hw(far ? d : 0.1f) - l2dc);
     if (far) de -= w[1] * inv_d;
   }
-  if ((flags & 1u) && d2 < 3.4f * 3.4f) {
+  // few slots hold a donor/acceptor pair inside 3.4 A: the term is skipped
+  // unless some lane of the wave needs it
+  const bool hb_in = (flags & 1u) && d2 < 3.4f * 3.4f;
+  if (__builtin_amdgcn_ballot_w64(hb_in)) {
     const float t = d - 2.88f;
-    const float eh = exp2_hw(t * t * (-kLog2e / 0.18f));
+    const float eh = hb_in ? exp2_hw(t * t * (-kLog2e / 0.18f)) : 0.f;
     e -= w[2] * eh;
     de += (w[2] * (2.0f / 0.18f)) * t * eh;
   }
@@ -667,15 +683,16 @@ struct Rigid {
   float Tx, Ty, Tz, sa, ca, sb, cb;
 };
 
-// Forward kinematics: world coordinates of the atoms owned by lane r.
-// Fragment transforms are composed root-to-leaf by pointer jumping
-// (ceil(log2) rounds of "compose with my current ancestor's transform").
-// With T4 (LDS, 3 * LPP float4 of the group) the transforms are exchanged as
-// three float4 rows per fragment (3 stores + 3 loads per round, 3 loads per
-// atom) instead of one shuffle per element; without it, by shuffles only.
+// Forward kinematics, first half: the local transform of the fragment owned
+// by lane r (the world rotation and translation for the root; a Rodrigues
+// rotation about the torsion axis for the others) as 3 x 4 rows.
+struct LocalTf {
+  float m[9], t[3];
+  Rigid rg;
+};
 template <int LPP, int APL>
-DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][3],
-                         float4* T4 = nullptr) {
+DK_INLINE LocalTf fk_local(const LaneLig<APL>& L, float q, int r) {
+  LocalTf o;
   // ---- each lane takes sin/cos of its own angle DOF once; the rigid part
   // and every fragment's torsion are then fetched from the owning lanes
   float sq, cq;
@@ -684,11 +701,10 @@ DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][
   const float sa = bcast<LPP>(sq, 3), ca = bcast<LPP>(cq, 3);
   const float sb = bcast<LPP>(sq, 4), cb = bcast<LPP>(cq, 4);
   const float sg = bcast<LPP>(sq, 5), cg = bcast<LPP>(cq, 5);
-  // ---- fragment transforms: lane f starts from its own local transform
   const int tsrc = bp_addr<LPP>(L.fdof >= 0 ? L.fdof : 0);
   const float st = bp(tsrc, sq), ct = bp(tsrc, cq);
-  float m[9], t[3];
-  int anc = L.fparent;
+  float* m = o.m;
+  float* t = o.t;
   if (L.fparent < 0) {
     // root (and idle lanes): world rotation R = Rz Ry Rx about c0, which is
     // the origin of the stored coordinates, so the translation is T itself
@@ -708,82 +724,109 @@ DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][
     t[1] = L.fxb[1] - (m[3] * L.fxb[0] + m[4] * L.fxb[1] + m[5] * L.fxb[2]);
     t[2] = L.fxb[2] - (m[6] * L.fxb[0] + m[7] * L.fxb[1] + m[8] * L.fxb[2]);
   }
-  // pointer jumping: C_f <- C_anc o C_f until every fragment reaches the root
-  auto compose = [&](const float (&a)[9], const float (&b)[3]) {
-    float nm[9], nt[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-        nm[3 * i + j] = a[3 * i] * m[j] + a[3 * i + 1] * m[3 + j] + a[3 * i + 2] * m[6 + j];
-      nt[i] = a[3 * i] * t[0] + a[3 * i + 1] * t[1] + a[3 * i + 2] * t[2] + b[i];
-    }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) m[k] = nm[k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) t[k] = nt[k];
-  };
-  if (T4) {
-    for (int it = 0; it < L.fk_rounds; ++it) {
-      T4[r] = make_float4(m[0], m[1], m[2], t[0]);
-      T4[LPP + r] = make_float4(m[3], m[4], m[5], t[1]);
-      T4[2 * LPP + r] = make_float4(m[6], m[7], m[8], t[2]);
-      wave_sync();
-      const int src = anc >= 0 ? anc : r;
-      const int anc2 = bp(bp_addr<LPP>(src), anc);
-      const float4 r0 = T4[src], r1 = T4[LPP + src], r2 = T4[2 * LPP + src];
-      wave_sync();
-      if (anc >= 0) {
-        const float a[9] = {r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, r2.x, r2.y, r2.z};
-        const float b[3] = {r0.w, r1.w, r2.w};
-        compose(a, b);
-        anc = anc2;
-      }
-    }
-    T4[r] = make_float4(m[0], m[1], m[2], t[0]);
-    T4[LPP + r] = make_float4(m[3], m[4], m[5], t[1]);
-    T4[2 * LPP + r] = make_float4(m[6], m[7], m[8], t[2]);
+  o.rg.Tx = Tx; o.rg.Ty = Ty; o.rg.Tz = Tz;
+  o.rg.sa = sa; o.rg.ca = ca; o.rg.sb = sb; o.rg.cb = cb;
+  return o;
+}
+
+// C = A o M for 3 x 4 rows (rotation | translation).
+DK_INLINE void compose_rows(const float4& a0, const float4& a1, const float4& a2, const float4& m0,
+                            const float4& m1, const float4& m2, float4& c0, float4& c1, float4& c2) {
+  c0 = make_float4(a0.x * m0.x + a0.y * m1.x + a0.z * m2.x, a0.x * m0.y + a0.y * m1.y + a0.z * m2.y,
+                   a0.x * m0.z + a0.y * m1.z + a0.z * m2.z, a0.x * m0.w + a0.y * m1.w + a0.z * m2.w + a0.w);
+  c1 = make_float4(a1.x * m0.x + a1.y * m1.x + a1.z * m2.x, a1.x * m0.y + a1.y * m1.y + a1.z * m2.y,
+                   a1.x * m0.z + a1.y * m1.z + a1.z * m2.z, a1.x * m0.w + a1.y * m1.w + a1.z * m2.w + a1.w);
+  c2 = make_float4(a2.x * m0.x + a2.y * m1.x + a2.z * m2.x, a2.x * m0.y + a2.y * m1.y + a2.z * m2.y,
+                   a2.x * m0.z + a2.y * m1.z + a2.z * m2.z, a2.x * m0.w + a2.y * m1.w + a2.z * m2.w + a2.w);
+}
+
+// Forward kinematics: world coordinates of the atoms owned by lane r.
+// Fragment transforms are composed root-to-leaf by pointer jumping
+// (ceil(log2) rounds of "compose with my current ancestor's transform").  The
+// transforms live in LDS as three float4 rows per fragment (T4: 3 * LPP
+// float4 of the group): each round reads the fragment's own and its
+// ancestor's rows and writes the product back, so nothing is carried in
+// registers from round to round.
+template <int LPP, int APL>
+DK_INLINE Rigid fk_place(const LaneLig<APL>& L, float q, int r, float (&x)[APL][3], float4* T4) {
+  const LocalTf lt = fk_local<LPP, APL>(L, q, r);
+  int anc = L.fparent;
+  T4[r] = make_float4(lt.m[0], lt.m[1], lt.m[2], lt.t[0]);
+  T4[LPP + r] = make_float4(lt.m[3], lt.m[4], lt.m[5], lt.t[1]);
+  T4[2 * LPP + r] = make_float4(lt.m[6], lt.m[7], lt.m[8], lt.t[2]);
+  for (int it = 0; it < L.fk_rounds; ++it) {
     wave_sync();
-#pragma unroll
-    for (int s = 0; s < APL; ++s) {
-      const int f = L.afrag[s];
-      const float4 r0 = T4[f], r1 = T4[LPP + f], r2 = T4[2 * LPP + f];
-      x[s][0] = r0.x * L.ax[s] + r0.y * L.ay[s] + r0.z * L.az[s] + r0.w;
-      x[s][1] = r1.x * L.ax[s] + r1.y * L.ay[s] + r1.z * L.az[s] + r1.w;
-      x[s][2] = r2.x * L.ax[s] + r2.y * L.ay[s] + r2.z * L.az[s] + r2.w;
-    }
-    wave_sync();  // the rows are overwritten by the caller's coordinate slab
-  } else {
-    for (int it = 0; it < L.fk_rounds; ++it) {
-      const int ad = bp_addr<LPP>(anc >= 0 ? anc : r);
-      float a[9], b[3];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) a[k] = bp(ad, m[k]);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) b[k] = bp(ad, t[k]);
-      const int anc2 = bp(ad, anc);
-      if (anc >= 0) {
-        compose(a, b);
-        anc = anc2;
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < APL; ++s) {
-      const int ad = bp_addr<LPP>(L.afrag[s]);
-      float a[9], b[3];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) a[k] = bp(ad, m[k]);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) b[k] = bp(ad, t[k]);
-      x[s][0] = a[0] * L.ax[s] + a[1] * L.ay[s] + a[2] * L.az[s] + b[0];
-      x[s][1] = a[3] * L.ax[s] + a[4] * L.ay[s] + a[5] * L.az[s] + b[1];
-      x[s][2] = a[6] * L.ax[s] + a[7] * L.ay[s] + a[8] * L.az[s] + b[2];
+    const int src = anc >= 0 ? anc : r;
+    const int anc2 = bp(bp_addr<LPP>(src), anc);
+    const float4 a0 = T4[src], a1 = T4[LPP + src], a2 = T4[2 * LPP + src];
+    const float4 m0 = T4[r], m1 = T4[LPP + r], m2 = T4[2 * LPP + r];
+    wave_sync();
+    if (anc >= 0) {
+      float4 c0, c1, c2;
+      compose_rows(a0, a1, a2, m0, m1, m2, c0, c1, c2);
+      T4[r] = c0;
+      T4[LPP + r] = c1;
+      T4[2 * LPP + r] = c2;
+      anc = anc2;
     }
   }
-  Rigid rg;
-  rg.Tx = Tx; rg.Ty = Ty; rg.Tz = Tz;
-  rg.sa = sa; rg.ca = ca; rg.sb = sb; rg.cb = cb;
-  return rg;
+  wave_sync();
+#pragma unroll
+  for (int s = 0; s < APL; ++s) {
+    const int f = L.afrag[s];
+    const float4 r0 = T4[f], r1 = T4[LPP + f], r2 = T4[2 * LPP + f];
+    x[s][0] = r0.x * L.ax[s] + r0.y * L.ay[s] + r0.z * L.az[s] + r0.w;
+    x[s][1] = r1.x * L.ax[s] + r1.y * L.ay[s] + r1.z * L.az[s] + r1.w;
+    x[s][2] = r2.x * L.ax[s] + r2.y * L.ay[s] + r2.z * L.az[s] + r2.w;
+  }
+  wave_sync();  // the rows are overwritten by the caller's coordinate slab
+  return lt.rg;
+}
+
+// fk_place by cross-lane shuffles only (no LDS), for kernels without a slab.
+template <int LPP, int APL>
+DK_INLINE Rigid fk_place_shfl(const LaneLig<APL>& L, float q, int r, float (&x)[APL][3]) {
+  LocalTf lt = fk_local<LPP, APL>(L, q, r);
+  float* m = lt.m;
+  float* t = lt.t;
+  int anc = L.fparent;
+  for (int it = 0; it < L.fk_rounds; ++it) {
+    const int ad = bp_addr<LPP>(anc >= 0 ? anc : r);
+    float a[9], b[3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = bp(ad, m[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) b[k] = bp(ad, t[k]);
+    const int anc2 = bp(ad, anc);
+    if (anc >= 0) {
+      float nm[9], nt[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          nm[3 * i + j] = a[3 * i] * m[j] + a[3 * i + 1] * m[3 + j] + a[3 * i + 2] * m[6 + j];
+        nt[i] = a[3 * i] * t[0] + a[3 * i + 1] * t[1] + a[3 * i + 2] * t[2] + b[i];
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) m[k] = nm[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t[k] = nt[k];
+      anc = anc2;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < APL; ++s) {
+    const int ad = bp_addr<LPP>(L.afrag[s]);
+    float a[9], b[3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = bp(ad, m[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) b[k] = bp(ad, t[k]);
+    x[s][0] = a[0] * L.ax[s] + a[1] * L.ay[s] + a[2] * L.az[s] + b[0];
+    x[s][1] = a[3] * L.ax[s] + a[4] * L.ay[s] + a[5] * L.az[s] + b[1];
+    x[s][2] = a[6] * L.ax[s] + a[7] * L.ay[s] + a[8] * L.az[s] + b[2];
+  }
+  return lt.rg;
 }
 
 // Chain rule from atom gradients g (world frame) to the DOF held by lane r:
@@ -810,7 +853,7 @@ DK_INLINE float chain_rule(const LaneLig<APL>& L, const Rigid& rg, const float (
     vs[s][4] = rz * g[s][0] - rx * g[s][2];
     vs[s][5] = rx * g[s][1] - ry * g[s][0];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] += vs[s][k];
+    for (int k = 0; k < 6; ++k) v[k] = s == 0 ? vs[0][k] : v[k] + vs[s][k];
   }
   // inclusive scan over lanes (lane r covers atoms up to APL*r + APL - 1)
 #pragma unroll
@@ -905,7 +948,8 @@ DK_INLINE float pair_force_slot(const LaneLig<APL>& L, const uint4& rp, const f3
                                 float (&f)[3]) {
   const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
   const float d2 = dx * dx + dy * dy + dz * dz;
-  const float inv_d = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
+  // d2 = 0 (coincident atoms) gives d = 0 and a finite 1/d
+  const float inv_d = __builtin_amdgcn_rsqf(fmaxf(d2, 1e-30f));
   const float d = d2 * inv_d;
   const float rsum = __uint_as_float(rp.y);
   float e, de;
@@ -967,17 +1011,18 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
 #pragma unroll
   for (int s = 0; s < APL; ++s) fsum[s][0] = fsum[s][1] = fsum[s][2] = 0.f;
   if (APL == 1 && L.n_pass > 0) {
-    // ---- pass layout: lane r evaluates slot r of every pass and stores +f
-    // and -f of its pair in force entries r and W + r; then every atom lane
-    // sums the 4 (or 8) entries its pull word names (unused bytes name the
-    // zero entry 2W).  Plain stores and a fixed summation order: the result
-    // does not depend on timing.
+    // ---- pass layout: lane r evaluates slot r of every pass and stores the
+    // force on its pair's first endpoint in entry r; then every atom lane
+    // adds the entries named by the first half of its pull word and
+    // subtracts those named by the second half (2 + 2 or 4 + 4 entries;
+    // unused bytes name the zero entry W).  Plain stores and a fixed
+    // summation order: the result does not depend on timing.
     const int W = L.pass_w;
     const bool slot_lane = r < W;
     const uint4* recs = reinterpret_cast<const uint4*>(pairs);
     const uint2* pulls = reinterpret_cast<const uint2*>(pairs + 2 * L.n_prec);
     const uint32_t xs_a = lds_addr(S.xs), fb_a = lds_addr(S.fb);
-    if (r == 0) S.fb[2 * W] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r == 0) S.fb[W] = make_float4(0.f, 0.f, 0.f, 0.f);
     // the next pass's record and pull word are read before this pass's
     // gather, so their latency overlaps the gather and the sums
     const int lane_slot = slot_lane ? r : 0;
@@ -994,7 +1039,6 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
       if (slot_lane) {
         e_lane += e;
         lds_write4(fb_a + 16u * uint32_t(r), f[0], f[1], f[2]);
-        lds_write4(fb_a + 16u * uint32_t(W + r), -f[0], -f[1], -f[2]);
       }
       const int next = (ps + 1 < L.n_pass ? ps + 1 : ps) * W + lane_slot;
       rp_next = recs[next];
@@ -1005,20 +1049,25 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
 #pragma unroll
       for (int c = 0; c < 4; ++c) v[c] = lds_read4(lds_entry16_k(pw.x, c, fb_a));
       if (L.pull_cap > 4) {
+        // bytes 0-3 added, 4-7 subtracted
 #pragma unroll
         for (int c = 4; c < 8; ++c) v[c] = lds_read4(lds_entry16_k(pw.y, c & 3, fb_a));
 #pragma unroll
-        for (int c = 4; c < 8; ++c) {
-          fsum[0][0] += v[c].x;
-          fsum[0][1] += v[c].y;
-          fsum[0][2] += v[c].z;
+        for (int c = 0; c < 8; ++c) {
+          const float sg = c < 4 ? 1.f : -1.f;
+          fsum[0][0] += sg * v[c].x;
+          fsum[0][1] += sg * v[c].y;
+          fsum[0][2] += sg * v[c].z;
         }
-      }
+      } else {
+        // bytes 0-1 added, 2-3 subtracted
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        fsum[0][0] += v[c].x;
-        fsum[0][1] += v[c].y;
-        fsum[0][2] += v[c].z;
+        for (int c = 0; c < 4; ++c) {
+          const float sg = c < 2 ? 1.f : -1.f;
+          fsum[0][0] += sg * v[c].x;
+          fsum[0][1] += sg * v[c].y;
+          fsum[0][2] += sg * v[c].z;
+        }
       }
       wave_sync();
     }

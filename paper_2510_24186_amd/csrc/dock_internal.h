@@ -142,12 +142,14 @@ void type_pair_table(int preset, TypePair table[kTypes * kTypes]);
 // Intra-pair passes for groups whose lanes each own one atom.  A pass is
 // `width` slots (one per lane); slot s of pass k holds pair
 // (slot_i, slot_j)[k * width + s], or -1 for an empty slot.  Every pair is in
-// exactly one slot, and no atom is an endpoint of more than `cap` slots of a
-// pass.  Each pass the lane of slot s stores +f at force entry s and -f at
-// entry width + s (entry 2 * width holds zero); pulls[k * width + a] names,
-// byte by byte, the entries atom a sums: s where it is the pair's first
-// endpoint, width + s where it is the second, 2 * width past the end of its
-// list.  Plain stores and gathers: no LDS atomics.
+// exactly one slot (in either orientation), and within a pass no atom is the
+// first endpoint of more than cap / 2 slots nor the second endpoint of more
+// than cap / 2.  Each pass the lane of slot s stores the pair force f (on its
+// first endpoint) at entry s; entry `width` holds zero.  pulls[k * width + a]
+// names, byte by byte, the entries atom a adds (bytes 0 .. cap/2 - 1: slots
+// where it is the first endpoint) and subtracts (bytes cap/2 .. cap - 1:
+// slots where it is the second); unused bytes name the zero entry.  Plain
+// stores and gathers: no LDS atomics.
 constexpr int kMaxPull = 8;
 struct PassPlan {
   int n_pass = 0, cap = 0;

@@ -706,7 +706,7 @@ __global__ void __launch_bounds__(64) best_kernel(BestArgs a) {
     const int t = kI[c];
     const float q = r < lg.n_dof ? a.q_best[(size_t(lig) * T + t) * a.q_stride + r] : 0.f;
     float x[APL][3];
-    fk_place<LPP, APL>(L, q, r, x);
+    fk_place_shfl<LPP, APL>(L, q, r, x);
     bool dup = false;
     for (int k = 0; k < n_kept && !dup; ++k) {
       float acc = 0.f;

@@ -409,22 +409,58 @@ PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vec
     const auto cost = [](const PassPlan& q) { return q.n_pass * (12 + (q.cap <= 4 ? 4 : 8)); };
     if (cost(p8) < cost(plan)) plan = std::move(p8);
   }
-  // pull lists: per pass and atom, the force entries of its pairs (slot s
-  // for the first endpoint, width + s for the second); unused bytes name the
-  // zero entry 2 * width
-  const uint64_t none = uint64_t(2 * width) * 0x0101010101010101ull;
-  plan.pulls.assign(size_t(plan.n_pass) * width, none);
-  std::vector<int> k_of(n_atoms);
+  // Orientation: within a pass every atom is the first endpoint of at most
+  // half its pairs rounded up, and the second endpoint of at most as many
+  // (trails between odd-degree atoms, then closed trails, each pair pointing
+  // along its trail).  With at most `cap` pairs per atom, neither list
+  // exceeds cap / 2.
+  const int half = plan.cap / 2;
+  std::vector<std::vector<std::pair<int, int>>> adj(n_atoms);  // (other atom, slot)
+  std::vector<char> used(width);
+  std::vector<int> next_edge(n_atoms);
   for (int ps = 0; ps < plan.n_pass; ++ps) {
-    std::fill(k_of.begin(), k_of.end(), 0);
-    for (int s = 0; s < width; ++s) {
-      const int a = plan.slot_i[size_t(ps) * width + s], b = plan.slot_j[size_t(ps) * width + s];
+    const size_t base = size_t(ps) * width;
+    for (auto& v : adj) v.clear();
+    for (int sl = 0; sl < width; ++sl) {
+      const int a = plan.slot_i[base + sl], b = plan.slot_j[base + sl];
+      if (a < 0) continue;
+      adj[a].push_back({b, sl});
+      adj[b].push_back({a, sl});
+    }
+    std::fill(used.begin(), used.end(), 0);
+    std::fill(next_edge.begin(), next_edge.end(), 0);
+    auto walk = [&](int v) {
+      for (;;) {
+        while (next_edge[v] < int(adj[v].size()) && used[adj[v][next_edge[v]].second]) ++next_edge[v];
+        if (next_edge[v] == int(adj[v].size())) return;
+        const auto [w, sl] = adj[v][next_edge[v]];
+        used[sl] = 1;
+        plan.slot_i[base + sl] = v;  // the pair points from v to w
+        plan.slot_j[base + sl] = w;
+        v = w;
+      }
+    };
+    for (int v = 0; v < n_atoms; ++v)
+      if (adj[v].size() % 2) walk(v);
+    for (int v = 0; v < n_atoms; ++v) walk(v);
+  }
+  // pull lists: per pass and atom, byte k < cap / 2 names a slot where the
+  // atom is the first endpoint (+f), byte cap / 2 + k one where it is the
+  // second (-f); unused bytes name the zero entry `width`
+  const uint64_t none = uint64_t(width) * 0x0101010101010101ull;
+  plan.pulls.assign(size_t(plan.n_pass) * width, none);
+  std::vector<int> n_plus(n_atoms), n_minus(n_atoms);
+  for (int ps = 0; ps < plan.n_pass; ++ps) {
+    std::fill(n_plus.begin(), n_plus.end(), 0);
+    std::fill(n_minus.begin(), n_minus.end(), 0);
+    for (int sl = 0; sl < width; ++sl) {
+      const int a = plan.slot_i[size_t(ps) * width + sl], b = plan.slot_j[size_t(ps) * width + sl];
       if (a < 0) continue;
       uint64_t& la = plan.pulls[size_t(ps) * width + a];
       uint64_t& lb = plan.pulls[size_t(ps) * width + b];
-      const int ka = 8 * k_of[a]++, kb = 8 * k_of[b]++;
-      la = (la & ~(0xffull << ka)) | (uint64_t(s) << ka);
-      lb = (lb & ~(0xffull << kb)) | (uint64_t(width + s) << kb);
+      const int ka = 8 * n_plus[a]++, kb = 8 * (half + n_minus[b]++);
+      la = (la & ~(0xffull << ka)) | (uint64_t(sl) << ka);
+      lb = (lb & ~(0xffull << kb)) | (uint64_t(sl) << kb);
     }
   }
   return plan;
