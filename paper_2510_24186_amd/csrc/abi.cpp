@@ -155,6 +155,19 @@ static LaneCfg lane_cfg(const LigDev& lg, int force_lpp) {
   return c;
 }
 
+// One lane configuration wide enough for every ligand of a handle (the score
+// and differentiable kernels launch one grid).
+static LaneCfg wide_cfg(const dock_ligands_s* L) {
+  LaneCfg w{16, 1};
+  for (const LigDev& g : L->h_ligs) {
+    const LaneCfg c = lane_cfg(g, 0);
+    w.lpp = std::max(w.lpp, c.lpp);
+    w.apl = std::max(w.apl, c.apl);
+  }
+  if (w.apl == 2) w.lpp = 64;
+  return w;
+}
+
 // Autotuner choices per natural lane configuration (lpp, apl): the group
 // width and block size that measured fastest, process-wide, per device arch.
 struct TuneChoice {
@@ -576,13 +589,18 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
       return u;
     };
     const LaneCfg lc = lane_cfg(g, 0);
-    if (lc.apl == 1 && !pi_new.empty()) {
-      const PassPlan plan = schedule_passes(H.n_atoms, pi_new, pj_new, lc.lpp);
+    PassPlan plan;
+    if (!pi_new.empty()) plan = schedule_passes(H.n_atoms, pi_new, pj_new, lc.lpp, lc.apl);
+    // the pass layout stages 2 entries per slot and one per pull word; with
+    // two atoms per lane it is kept only where it fits the LDS budget
+    const size_t pass_entries = plan.slot_i.size() * 2 + plan.pulls.size();
+    if (plan.n_pass > 0 && (lc.apl == 1 || pass_entries * sizeof(PairRec) <= kPassStageBytes)) {
       g.n_pass = plan.n_pass;
       g.pass_w = lc.lpp;
+      g.pass_apl = lc.apl;
       g.pull_cap = plan.cap;
       // 16-byte slot records (pair word, radius sum, d_clash^2 as the device
-      // squares it, log2 d_clash), then one pull word per slot
+      // squares it, log2 d_clash), then the pull words (apl * width per pass)
       for (size_t s = 0; s < plan.slot_i.size(); ++s) {
         const int i0 = plan.slot_i[s], j0 = plan.slot_j[s];
         pairs.push_back(record(i0, j0));
@@ -594,7 +612,7 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
         }
         pairs.push_back(cl);
       }
-      for (size_t s = 0; s < plan.slot_i.size(); ++s) {
+      for (size_t s = 0; s < plan.pulls.size(); ++s) {
         PairRec pw;
         pw.w = uint32_t(plan.pulls[s]);
         const uint32_t hi = uint32_t(plan.pulls[s] >> 32);
@@ -783,14 +801,8 @@ int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligand
   const PocketDev* tab = nullptr;
   rc = pocket_table(pockets, n_pockets, &tab);
   if (rc) return rc;
-  // one lane configuration wide enough for every ligand of the handle
-  int lpp = 16, apl = 1;
-  for (const LigDev& g : L->h_ligs) {
-    LaneCfg c = lane_cfg(g, 0);
-    lpp = std::max(lpp, c.lpp);
-    apl = std::max(apl, c.apl);
-  }
-  if (apl == 2) lpp = 64;
+  const LaneCfg wc = wide_cfg(L);
+  const int lpp = wc.lpp, apl = wc.apl;
   if (score_lds_bytes(lpp, apl, L->max_pairs) > 64 * 1024)
     return fail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
   ScoreArgs a{};
@@ -846,13 +858,8 @@ static int terms_call(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
     a.G[i] = gi;
     a.dLdG[i] = dLdG ? dLdG[i] : nullptr;
   }
-  int lpp = 16, apl = 1;
-  for (const LigDev& g : L->h_ligs) {
-    LaneCfg c = lane_cfg(g, 0);
-    lpp = std::max(lpp, c.lpp);
-    apl = std::max(apl, c.apl);
-  }
-  if (apl == 2) lpp = 64;
+  const LaneCfg wc = wide_cfg(L);
+  const int lpp = wc.lpp, apl = wc.apl;
   if (score_lds_bytes(lpp, apl, L->max_pairs) > 64 * 1024)
     return fail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
   a.L = L->arrays();

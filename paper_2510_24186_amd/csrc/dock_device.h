@@ -567,7 +567,7 @@ DK_INLINE void mdn_term(const PocketDev& pk, const MdnArg& m, int atom, float px
 template <int APL>
 struct LaneLig {
   int n_atoms, n_frags, n_dof, n_prec, fk_rounds, preset;
-  int n_pass, pass_w, pull_cap;  // pass layout of the pair records (n_pass = 0: strided)
+  int n_pass, pass_w, pull_cap, pass_apl;  // pass layout of the pair records (n_pass = 0: strided)
   // atoms owned by this lane
   float ax[APL], ay[APL], az[APL];
   int atype[APL], afrag[APL], aorig[APL];
@@ -591,6 +591,7 @@ DK_INLINE void load_lane_lig(LaneLig<APL>& L, const LigDev& lg, const LigDev* __
   L.n_pass = lg.n_pass;
   L.pass_w = lg.pass_w;
   L.pull_cap = lg.pull_cap;
+  L.pass_apl = lg.pass_apl;
   L.fk_rounds = lg.fk_rounds;
   L.preset = pk.preset;
 #pragma unroll
@@ -964,6 +965,28 @@ DK_INLINE float pair_force_slot(const LaneLig<APL>& L, const uint4& rp, const f3
   return e;
 }
 
+// Pass-layout gather: each atom of the lane reads CAP force entries (bytes
+// 0 .. CAP/2 - 1 of its pull word are added, the rest subtracted; CAP = 8
+// spans both words), all reads issued before the first sum.
+template <int APL, int CAP>
+DK_INLINE void gather_forces(const uint2 (&pw)[APL], uint32_t fb_a, float (&fsum)[APL][3]) {
+  f32x4_t v[APL][CAP];
+#pragma unroll
+  for (int s = 0; s < APL; ++s)
+#pragma unroll
+    for (int c = 0; c < CAP; ++c)
+      v[s][c] = lds_read4(lds_entry16_k((CAP == 8 && c >= 4) ? pw[s].y : pw[s].x, c & 3, fb_a));
+#pragma unroll
+  for (int s = 0; s < APL; ++s)
+#pragma unroll
+    for (int c = 0; c < CAP; ++c) {
+      const float sg = c < CAP / 2 ? 1.f : -1.f;
+      fsum[s][0] += sg * v[s][c].x;
+      fsum[s][1] += sg * v[s][c].y;
+      fsum[s][2] += sg * v[s][c].z;
+    }
+}
+
 // One evaluation of E and dE/dq at the pose whose DOF r is held by lane r.
 // Optionally leaves world coordinates and atom gradients in xo/go; adds the
 // E_MDN term when mdn.par is set.
@@ -1010,28 +1033,43 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
   float fsum[APL][3];
 #pragma unroll
   for (int s = 0; s < APL; ++s) fsum[s][0] = fsum[s][1] = fsum[s][2] = 0.f;
-  if (APL == 1 && L.n_pass > 0) {
+  if (L.n_pass > 0 && L.pass_apl == APL && (APL == 1 || L.pass_w == LPP)) {
     // ---- pass layout: lane r evaluates slot r of every pass and stores the
-    // force on its pair's first endpoint in entry r; then every atom lane
-    // adds the entries named by the first half of its pull word and
-    // subtracts those named by the second half (2 + 2 or 4 + 4 entries;
-    // unused bytes name the zero entry W).  Plain stores and a fixed
-    // summation order: the result does not depend on timing.
+    // force on its pair's first endpoint in entry r; then each atom adds the
+    // entries named by the first half of its pull word and subtracts those
+    // named by the second half (1 + 1, 2 + 2 or 4 + 4 entries; unused bytes
+    // name the zero entry W).  Plain stores and a fixed summation order: the
+    // result does not depend on timing.
     const int W = L.pass_w;
     const bool slot_lane = r < W;
     const uint4* recs = reinterpret_cast<const uint4*>(pairs);
+    // pull words: one per atom, APL * W per pass; with two atoms per lane
+    // the lane's two words are adjacent and read as one 16-byte load
     const uint2* pulls = reinterpret_cast<const uint2*>(pairs + 2 * L.n_prec);
     const uint32_t xs_a = lds_addr(S.xs), fb_a = lds_addr(S.fb);
     if (r == 0) S.fb[W] = make_float4(0.f, 0.f, 0.f, 0.f);
-    // the next pass's record and pull word are read before this pass's
-    // gather, so their latency overlaps the gather and the sums
-    const int lane_slot = slot_lane ? r : 0;
-    uint4 rp_next = recs[lane_slot];
+    const int cap = L.pull_cap;
     // lanes without a slot hold no atom either: their gather is unused
-    uint2 pw_next = pulls[lane_slot];
+    const int lane_slot = slot_lane ? r : 0;
+    auto pull_words = [&](int ps, uint2 (&pw)[APL]) {
+      if (APL == 1) {
+        pw[0] = pulls[ps * W + lane_slot];
+      } else {
+        const uint4 q = reinterpret_cast<const uint4*>(pulls)[ps * W + r];
+        pw[0] = make_uint2(q.x, q.y);
+        pw[APL - 1] = make_uint2(q.z, q.w);
+      }
+    };
+    // the next pass's record and pull words are read before this pass's
+    // gather, so their latency overlaps the gather and the sums
+    uint4 rp_next = recs[lane_slot];
+    uint2 pw_next[APL];
+    pull_words(0, pw_next);
     for (int ps = 0; ps < L.n_pass; ++ps) {
       const uint4 rp = rp_next;
-      const uint2 pw = pw_next;
+      uint2 pw[APL];
+#pragma unroll
+      for (int s = 0; s < APL; ++s) pw[s] = pw_next[s];
       const f32x4_t xi = lds_read4(lds_entry16<0>(rp.x, xs_a));
       const f32x4_t xj = lds_read4(lds_entry16<1>(rp.x, xs_a));
       float f[3];
@@ -1040,35 +1078,18 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
         e_lane += e;
         lds_write4(fb_a + 16u * uint32_t(r), f[0], f[1], f[2]);
       }
-      const int next = (ps + 1 < L.n_pass ? ps + 1 : ps) * W + lane_slot;
-      rp_next = recs[next];
-      pw_next = pulls[next];
+      const int next = ps + 1 < L.n_pass ? ps + 1 : ps;
+      rp_next = recs[next * W + lane_slot];
+      pull_words(next, pw_next);
       wave_sync();
-      // every entry is read before any is summed
-      f32x4_t v[kMaxPull];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] = lds_read4(lds_entry16_k(pw.x, c, fb_a));
-      if (L.pull_cap > 4) {
-        // bytes 0-3 added, 4-7 subtracted
-#pragma unroll
-        for (int c = 4; c < 8; ++c) v[c] = lds_read4(lds_entry16_k(pw.y, c & 3, fb_a));
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const float sg = c < 4 ? 1.f : -1.f;
-          fsum[0][0] += sg * v[c].x;
-          fsum[0][1] += sg * v[c].y;
-          fsum[0][2] += sg * v[c].z;
-        }
-      } else {
-        // bytes 0-1 added, 2-3 subtracted
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const float sg = c < 2 ? 1.f : -1.f;
-          fsum[0][0] += sg * v[c].x;
-          fsum[0][1] += sg * v[c].y;
-          fsum[0][2] += sg * v[c].z;
-        }
-      }
+      // every entry of the lane is read before any is summed
+      // caps: 4 or 8 with one atom per lane, 2 or 4 with two
+      if (APL == 2 && cap == 2)
+        gather_forces<APL, 2>(pw, fb_a, fsum);
+      else if (APL == 2 || cap == 4)
+        gather_forces<APL, 4>(pw, fb_a, fsum);
+      else
+        gather_forces<APL, 8>(pw, fb_a, fsum);
       wave_sync();
     }
   } else {

@@ -28,6 +28,7 @@ struct alignas(16) LigDev {
   float box_min[3];
   float box_max[3];
   int n_pass, pass_w, pull_cap;           // pass layout (n_pass = 0: pairs are strided, forces by atomics)
+  int pass_apl;                           // atoms per lane of the pass layout (pull words per pass = apl * w)
   int n_stage;                            // 8-byte entries to stage: pair records (+ pull words)
 };
 
@@ -139,24 +140,29 @@ int prepare_ligand(int n, const uint8_t* element, const uint8_t* n_h, const floa
 
 void type_pair_table(int preset, TypePair table[kTypes * kTypes]);
 
-// Intra-pair passes for groups whose lanes each own one atom.  A pass is
-// `width` slots (one per lane); slot s of pass k holds pair
+// Intra-pair passes for groups whose lanes each own `apl` (1 or 2) atoms.  A
+// pass is `width` slots (one per lane); slot s of pass k holds pair
 // (slot_i, slot_j)[k * width + s], or -1 for an empty slot.  Every pair is in
 // exactly one slot (in either orientation), and within a pass no atom is the
 // first endpoint of more than cap / 2 slots nor the second endpoint of more
 // than cap / 2.  Each pass the lane of slot s stores the pair force f (on its
-// first endpoint) at entry s; entry `width` holds zero.  pulls[k * width + a]
-// names, byte by byte, the entries atom a adds (bytes 0 .. cap/2 - 1: slots
-// where it is the first endpoint) and subtracts (bytes cap/2 .. cap - 1:
-// slots where it is the second); unused bytes name the zero entry.  Plain
-// stores and gathers: no LDS atomics.
+// first endpoint) at entry s; entry `width` holds zero.
+// pulls[k * n_pull + a] (n_pull = apl * width) names, byte by byte, the
+// entries atom a adds (bytes 0 .. cap/2 - 1: slots where it is the first
+// endpoint) and subtracts (bytes cap/2 .. cap - 1: slots where it is the
+// second); unused bytes name the zero entry.  Plain stores and gathers: no
+// LDS atomics.
 constexpr int kMaxPull = 8;
+// Staged bytes above which a two-atoms-per-lane ligand keeps its strided
+// pair list (8-byte records) instead of the pass layout.
+constexpr size_t kPassStageBytes = 40 * 1024;
 struct PassPlan {
-  int n_pass = 0, cap = 0;
+  int n_pass = 0, cap = 0, n_pull = 0;
   std::vector<int> slot_i, slot_j;
   std::vector<uint64_t> pulls;
 };
-PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vector<int>& pj, int width);
+PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vector<int>& pj, int width,
+                         int apl = 1);
 
 void preset_weights(int preset, float* w, int* K);
 

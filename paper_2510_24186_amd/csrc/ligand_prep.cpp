@@ -382,7 +382,8 @@ PassPlan plan_for_cap(int n_atoms, const std::vector<int>& pi, const std::vector
 
 }  // namespace
 
-PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vector<int>& pj, int width) {
+PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vector<int>& pj, int width,
+                         int apl) {
   PassPlan plan;
   const size_t P = pi.size();
   if (P == 0) return plan;
@@ -400,15 +401,22 @@ PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vec
     return long(hi) * (n_atoms + 1) + lo;
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) > key(b); });
-  // The gather reads 4 or 8 entries per pass.  Cost of a plan ~ passes x
-  // (pair work, about 12 gathered entries' worth, + entries read); the cap-8
-  // plan is kept only when it is cheaper.
-  plan = plan_for_cap(n_atoms, pi, pj, width, 4, order, max_deg);
-  if ((max_deg + 3) / 4 > (int(P) + width - 1) / width) {
-    PassPlan p8 = plan_for_cap(n_atoms, pi, pj, width, kMaxPull, order, max_deg);
-    const auto cost = [](const PassPlan& q) { return q.n_pass * (12 + (q.cap <= 4 ? 4 : 8)); };
-    if (cost(p8) < cost(plan)) plan = std::move(p8);
+  // Each atom's gather reads `cap` entries per pass: 4 or 8 with one atom
+  // per lane, 2 or 4 with two (the lane's 16 reads of 8 + 8 would not fit its
+  // registers).  Cost of a plan ~ passes x (pair work, about 12 gathered
+  // entries' worth, + entries read per lane); the cheapest cap is kept.  A
+  // larger cap only pays when the busiest atom, not the slot count, sets the
+  // number of passes.
+  const int min_pass = (int(P) + width - 1) / width;
+  const auto cost = [&](const PassPlan& q) { return q.n_pass * (12 + apl * q.cap); };
+  bool have = false;
+  for (int cap = apl == 1 ? 4 : 2; cap <= (apl == 1 ? kMaxPull : 4); cap *= 2) {
+    if (have && (max_deg + cap / 2 - 1) / (cap / 2) <= min_pass) break;  // the previous cap already met P / width
+    PassPlan q = plan_for_cap(n_atoms, pi, pj, width, cap, order, max_deg);
+    if (!have || cost(q) < cost(plan)) plan = std::move(q);
+    have = true;
   }
+  plan.n_pull = apl * width;
   // Orientation: within a pass every atom is the first endpoint of at most
   // half its pairs rounded up, and the second endpoint of at most as many
   // (trails between odd-degree atoms, then closed trails, each pair pointing
@@ -448,7 +456,7 @@ PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vec
   // atom is the first endpoint (+f), byte cap / 2 + k one where it is the
   // second (-f); unused bytes name the zero entry `width`
   const uint64_t none = uint64_t(width) * 0x0101010101010101ull;
-  plan.pulls.assign(size_t(plan.n_pass) * width, none);
+  plan.pulls.assign(size_t(plan.n_pass) * plan.n_pull, none);
   std::vector<int> n_plus(n_atoms), n_minus(n_atoms);
   for (int ps = 0; ps < plan.n_pass; ++ps) {
     std::fill(n_plus.begin(), n_plus.end(), 0);
@@ -456,8 +464,8 @@ PassPlan schedule_passes(int n_atoms, const std::vector<int>& pi, const std::vec
     for (int sl = 0; sl < width; ++sl) {
       const int a = plan.slot_i[size_t(ps) * width + sl], b = plan.slot_j[size_t(ps) * width + sl];
       if (a < 0) continue;
-      uint64_t& la = plan.pulls[size_t(ps) * width + a];
-      uint64_t& lb = plan.pulls[size_t(ps) * width + b];
+      uint64_t& la = plan.pulls[size_t(ps) * plan.n_pull + a];
+      uint64_t& lb = plan.pulls[size_t(ps) * plan.n_pull + b];
       const int ka = 8 * n_plus[a]++, kb = 8 * (half + n_minus[b]++);
       la = (la & ~(0xffull << ka)) | (uint64_t(sl) << ka);
       lb = (lb & ~(0xffull << kb)) | (uint64_t(sl) << kb);

@@ -168,9 +168,11 @@ def test_score_grad_c1(D, preset):
 
 
 def test_score_grad_ragged_all_lane_configs(D):
-    # sizes that select 16-, 32- and 64-lane groups and two atoms per lane
+    # sizes that select 16-, 32- and 64-lane groups and two atoms per lane;
+    # the 66-, 70- and 80-atom ligands have few torsions, so their pair lists
+    # fit the two-atoms-per-lane pass layout (the larger ones stay strided)
     spec = [(10, 0), (14, 9), (16, 10), (17, 2), (30, 12), (33, 3), (45, 15), (64, 20), (65, 4),
-            (90, 12), (128, 31)]
+            (66, 1), (70, 2), (80, 2), (90, 12), (128, 31)]
     parts = [synth.make_ligand(n, t, np.random.default_rng(40 + n)) for n, t in spec]
     L = synth.pack_ligands(parts)
     L.pocket_index = np.zeros(L.n_ligands, np.int32)
