@@ -143,20 +143,27 @@ struct LaneCfg {
   int lpp, apl;
 };
 
-// Smallest group that gives every DOF, fragment and atom (two per lane above
-// 64 atoms) a lane.
+// Smallest group that gives every DOF, fragment and atom a lane: one atom per
+// lane up to 32 atoms; two per lane above 64, and from 33 to 64 atoms when
+// the DOFs and fragments fit 32 lanes (two poses per wavefront then share the
+// per-pose work: FK transforms, scans, optimiser updates).
 static LaneCfg lane_cfg(const LigDev& lg, int force_lpp) {
   LaneCfg c;
-  c.apl = lg.n_atoms > 64 ? 2 : 1;
+  const bool mid = lg.n_atoms > 32 && lg.n_atoms <= 64 && lg.n_dof <= 32 && lg.n_frags <= 32;
+  c.apl = (lg.n_atoms > 64 || mid) ? 2 : 1;
   const int need = std::max({(lg.n_atoms + c.apl - 1) / c.apl, lg.n_dof, lg.n_frags});
   c.lpp = need <= 16 ? 16 : (need <= 32 ? 32 : 64);
-  if (c.apl == 2) c.lpp = 64;
+  if (lg.n_atoms > 64) c.lpp = 64;
   if (force_lpp > c.lpp && c.apl == 1) c.lpp = force_lpp;
   return c;
 }
 
 // One lane configuration wide enough for every ligand of a handle (the score
 // and differentiable kernels launch one grid).
+// Each group of these kernels stages its own pose's pair records, so two
+// 32-lane groups per 64-lane block need twice the pair budget; when that
+// exceeds the LDS, one 64-lane group per block is used (ligands laid out for
+// 32-lane groups then take the strided pair path).
 static LaneCfg wide_cfg(const dock_ligands_s* L) {
   LaneCfg w{16, 1};
   for (const LigDev& g : L->h_ligs) {
@@ -164,7 +171,8 @@ static LaneCfg wide_cfg(const dock_ligands_s* L) {
     w.lpp = std::max(w.lpp, c.lpp);
     w.apl = std::max(w.apl, c.apl);
   }
-  if (w.apl == 2) w.lpp = 64;
+  if (w.apl == 2) w.lpp = std::max(w.lpp, 32);
+  if (w.lpp < 64 && score_lds_bytes(w.lpp, w.apl, L->max_pairs) > 64 * 1024) w.lpp = 64;
   return w;
 }
 
@@ -591,9 +599,11 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
     const LaneCfg lc = lane_cfg(g, 0);
     PassPlan plan;
     if (!pi_new.empty()) plan = schedule_passes(H.n_atoms, pi_new, pj_new, lc.lpp, lc.apl);
-    // the pass layout stages 2 entries per slot and one per pull word; with
-    // two atoms per lane it is kept only where it fits the LDS budget
-    const size_t pass_entries = plan.slot_i.size() * 2 + plan.pulls.size();
+    // the pass layout stages 2 entries per slot and apl * cap pull bytes per
+    // lane and pass; with two atoms per lane it is kept only where it fits
+    // the LDS budget
+    const size_t pull_bytes = size_t(plan.n_pass) * lc.lpp * lc.apl * plan.cap;
+    const size_t pass_entries = plan.slot_i.size() * 2 + pull_bytes / sizeof(PairRec) + 1;
     if (plan.n_pass > 0 && (lc.apl == 1 || pass_entries * sizeof(PairRec) <= kPassStageBytes)) {
       g.n_pass = plan.n_pass;
       g.pass_w = lc.lpp;
@@ -607,18 +617,31 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
         PairRec cl{};
         if (i0 >= 0) {
           const TypePair& tp = tab[H.type[H.dfs_atom[i0]] * kTypes + H.type[H.dfs_atom[j0]]];
-          cl.w = bits(tp.dclash2);
+          // negated for a donor/acceptor pair: the kernel tests |d_clash^2|
+          // for the clash term and the sign for the hydrogen-bond term
+          cl.w = bits((tp.flags & 1u) ? -tp.dclash2 : tp.dclash2);
           cl.rsum = float(std::log2(double(tp.dclash)));
         }
         pairs.push_back(cl);
       }
-      for (size_t s = 0; s < plan.pulls.size(); ++s) {
+      // pull bytes per (pass, lane): the lane's atoms one after the other,
+      // the first `cap` bytes of each atom's pull list
+      std::vector<uint8_t> pb(pull_bytes);
+      const int per_lane = lc.apl * plan.cap;
+      for (int ps = 0; ps < plan.n_pass; ++ps)
+        for (int ln = 0; ln < lc.lpp; ++ln)
+          for (int sa = 0; sa < lc.apl; ++sa) {
+            const uint64_t w = plan.pulls[size_t(ps) * plan.n_pull + lc.apl * ln + sa];
+            for (int b = 0; b < plan.cap; ++b)
+              pb[(size_t(ps) * lc.lpp + ln) * per_lane + sa * plan.cap + b] = uint8_t(w >> (8 * b));
+          }
+      for (size_t o = 0; o < pb.size(); o += sizeof(PairRec)) {
         PairRec pw;
-        pw.w = uint32_t(plan.pulls[s]);
-        const uint32_t hi = uint32_t(plan.pulls[s] >> 32);
-        std::memcpy(&pw.rsum, &hi, 4);
+        std::memcpy(&pw, pb.data() + o, sizeof(PairRec));
         pairs.push_back(pw);
       }
+      // padding: the kernel reads each 4-byte pull word with its successor
+      pairs.push_back(PairRec{});
       g.n_prec = int(plan.slot_i.size());
     } else {
       for (size_t p = 0; p < pi_new.size(); ++p) pairs.push_back(record(pi_new[p], pj_new[p]));

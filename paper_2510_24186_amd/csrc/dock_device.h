@@ -144,13 +144,13 @@ DK_INLINE float group_scan(float v) {
 // Pair word: i | j << 8 | type_i << 16 | type_j << 20 | flags << 24, plus the
 // radius sum as a float.  flags bit0 donor/acceptor pair, bit1 both
 // hydrophobic, bit7 empty slot (no pair).
-// Pass layout (one atom per lane): each slot takes two entries, the pair word
-// and radius sum, then the E_clash constants d_clash^2 and log2(d_clash)
-// (FP32 bit patterns in a second PairRec), so record p still starts at entry
-// 2p; after the n_prec slots come the pull words, one 8-byte entry per slot
-// (the pull list of atom `slot` for the pass, see PassPlan).  An empty slot
-// names atoms 0 and 0 with a radius sum of -1e4 and zero clash constants,
-// which makes every term of both presets exactly zero.
+// Pass layout: each slot takes two entries, the pair word and radius sum,
+// then the E_clash constants d_clash^2 (negated for a donor/acceptor pair)
+// and log2(d_clash) (FP32 bit patterns in a second PairRec), so record p
+// still starts at entry 2p; after the n_prec slots come the pull words, one
+// 8-byte entry per atom and pass (see PassPlan).  An empty slot names atoms 0
+// and 0 with a radius sum of -1e4 and zero clash constants, which makes every
+// term of both presets exactly zero.
 constexpr uint32_t kPairEmpty = 0x80u << 24;
 constexpr float kEmptyRsum = -1.0e4f;
 struct PairRec {
@@ -247,24 +247,25 @@ DK_INLINE void trids_pair(float d2, float d, float rsum, uint32_t flags, const f
 }
 
 // The TRIDS terms as trids_pair, with the clash cutoff and log2 of the clash
-// distance taken from the slot record (dc2 = d_clash^2, l2dc = log2 d_clash):
-// -log(dd / dc) = -ln2 (log2 dd - log2 dc), and for d > 0.1 the derivative
-// -1/d comes from the caller's 1/d.
+// distance taken from the slot record (|dc2| = d_clash^2, negative for a
+// donor/acceptor pair; l2dc = log2 d_clash): -log(dd / dc) =
+// -ln2 (log2 dd - log2 dc), and for d > 0.1 the derivative -1/d comes from
+// the caller's 1/d.
 DK_INLINE void trids_pair_k(float d2, float d, float inv_d, float rsum, float dc2, float l2dc,
-                            uint32_t flags, const float* w, float& e, float& de) {
+                            const float* w, float& e, float& de) {
   const float s = d - rsum - 3.0f;
   float ex = exp2_hw(s * s * (-0.25f * kLog2e));
   ex = d2 < 100.0f ? ex : 0.f;
   e = -w[0] * ex;
   de = (w[0] * 0.5f) * s * ex;
-  if (d2 < dc2) {
+  if (d2 < fabsf(dc2)) {
     const bool far = d > 0.1f;
     e -= (w[1] * kLn2) * (log2_hw(far ? d : 0.1f) - l2dc);
     if (far) de -= w[1] * inv_d;
   }
   // few slots hold a donor/acceptor pair inside 3.4 A: the term is skipped
   // unless some lane of the wave needs it
-  const bool hb_in = (flags & 1u) && d2 < 3.4f * 3.4f;
+  const bool hb_in = (dc2 < 0.f) & (d2 < 3.4f * 3.4f);
   if (__builtin_amdgcn_ballot_w64(hb_in)) {
     const float t = d - 2.88f;
     const float eh = hb_in ? exp2_hw(t * t * (-kLog2e / 0.18f)) : 0.f;
@@ -905,7 +906,7 @@ DK_INLINE float chain_rule(const LaneLig<APL>& L, const Rigid& rg, const float (
     gq = ca * cb * St[0] + sa * cb * St[1] - sb * St[2];
   } else if (r < L.n_dof) {
     // axis atoms of this lane's torsion
-    const float4 xa = S.xs[L.ta], xb = S.xs[L.tb];
+    const f32x4_t xa = lds_read4(lds_addr(S.xs + L.ta)), xb = lds_read4(lds_addr(S.xs + L.tb));
     float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
     const float inv = __builtin_amdgcn_rsqf(ux * ux + uy * uy + uz * uz);
     ux *= inv; uy *= inv; uz *= inv;
@@ -955,7 +956,7 @@ DK_INLINE float pair_force_slot(const LaneLig<APL>& L, const uint4& rp, const f3
   const float rsum = __uint_as_float(rp.y);
   float e, de;
   if (L.preset == DOCK_PRESET_TRIDS)
-    trids_pair_k(d2, d, inv_d, rsum, __uint_as_float(rp.z), __uint_as_float(rp.w), rp.x >> 24, L.w, e, de);
+    trids_pair_k(d2, d, inv_d, rsum, __uint_as_float(rp.z), __uint_as_float(rp.w), L.w, e, de);
   else
     vina_pair(d2, d, rsum, rp.x >> 24, L.w, e, de);
   const float c = de * inv_d;
@@ -965,17 +966,31 @@ DK_INLINE float pair_force_slot(const LaneLig<APL>& L, const uint4& rp, const f3
   return e;
 }
 
-// Pass-layout gather: each atom of the lane reads CAP force entries (bytes
-// 0 .. CAP/2 - 1 of its pull word are added, the rest subtracted; CAP = 8
-// spans both words), all reads issued before the first sum.
+// Pass-layout gather: each atom of the lane reads CAP force entries, the
+// first CAP/2 added and the rest subtracted, all reads issued before the
+// first sum.  The lane's pull bytes (APL * CAP of them) are packed in pw:
+// CAP 8: x then y; CAP 4: atom s in word s; CAP 2: atom s in bytes 2s, 2s+1.
 template <int APL, int CAP>
-DK_INLINE void gather_forces(const uint2 (&pw)[APL], uint32_t fb_a, float (&fsum)[APL][3]) {
+DK_INLINE void gather_forces(const uint2& pw, uint32_t fb_a, float (&fsum)[APL][3]) {
   f32x4_t v[APL][CAP];
 #pragma unroll
   for (int s = 0; s < APL; ++s)
 #pragma unroll
-    for (int c = 0; c < CAP; ++c)
-      v[s][c] = lds_read4(lds_entry16_k((CAP == 8 && c >= 4) ? pw[s].y : pw[s].x, c & 3, fb_a));
+    for (int c = 0; c < CAP; ++c) {
+      uint32_t word;
+      int k;
+      if (CAP == 8) {
+        word = c < 4 ? pw.x : pw.y;
+        k = c & 3;
+      } else if (CAP == 4) {
+        word = s == 0 ? pw.x : pw.y;
+        k = c;
+      } else {
+        word = pw.x;
+        k = 2 * s + c;
+      }
+      v[s][c] = lds_read4(lds_entry16_k(word, k, fb_a));
+    }
 #pragma unroll
   for (int s = 0; s < APL; ++s)
 #pragma unroll
@@ -1043,33 +1058,29 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
     const int W = L.pass_w;
     const bool slot_lane = r < W;
     const uint4* recs = reinterpret_cast<const uint4*>(pairs);
-    // pull words: one per atom, APL * W per pass; with two atoms per lane
-    // the lane's two words are adjacent and read as one 16-byte load
-    const uint2* pulls = reinterpret_cast<const uint2*>(pairs + 2 * L.n_prec);
+    // pull bytes: APL * cap per lane and pass (4 or 8), the lane's atoms one
+    // after the other, read as one 4- or 8-byte word
+    const int cap = L.pull_cap;
+    const int wshift = APL * cap > 4 ? 1 : 0;
+    // two consecutive dwords are always read (one ds_read2_b32); with 4-byte
+    // words the second belongs to the next lane (or the padding entry the
+    // host stages after the pull bytes) and is unused
+    const uint32_t* pulls32 = reinterpret_cast<const uint32_t*>(pairs + 2 * L.n_prec);
     const uint32_t xs_a = lds_addr(S.xs), fb_a = lds_addr(S.fb);
     if (r == 0) S.fb[W] = make_float4(0.f, 0.f, 0.f, 0.f);
-    const int cap = L.pull_cap;
     // lanes without a slot hold no atom either: their gather is unused
     const int lane_slot = slot_lane ? r : 0;
-    auto pull_words = [&](int ps, uint2 (&pw)[APL]) {
-      if (APL == 1) {
-        pw[0] = pulls[ps * W + lane_slot];
-      } else {
-        const uint4 q = reinterpret_cast<const uint4*>(pulls)[ps * W + r];
-        pw[0] = make_uint2(q.x, q.y);
-        pw[APL - 1] = make_uint2(q.z, q.w);
-      }
+    auto pull_word = [&](int ps) {
+      const int j = (ps * W + lane_slot) << wshift;
+      return make_uint2(pulls32[j], pulls32[j + 1]);
     };
-    // the next pass's record and pull words are read before this pass's
+    // the next pass's record and pull word are read before this pass's
     // gather, so their latency overlaps the gather and the sums
     uint4 rp_next = recs[lane_slot];
-    uint2 pw_next[APL];
-    pull_words(0, pw_next);
+    uint2 pw_next = pull_word(0);
     for (int ps = 0; ps < L.n_pass; ++ps) {
       const uint4 rp = rp_next;
-      uint2 pw[APL];
-#pragma unroll
-      for (int s = 0; s < APL; ++s) pw[s] = pw_next[s];
+      const uint2 pw = pw_next;
       const f32x4_t xi = lds_read4(lds_entry16<0>(rp.x, xs_a));
       const f32x4_t xj = lds_read4(lds_entry16<1>(rp.x, xs_a));
       float f[3];
@@ -1080,10 +1091,10 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
       }
       const int next = ps + 1 < L.n_pass ? ps + 1 : ps;
       rp_next = recs[next * W + lane_slot];
-      pull_words(next, pw_next);
+      pw_next = pull_word(next);
       wave_sync();
-      // every entry of the lane is read before any is summed
-      // caps: 4 or 8 with one atom per lane, 2 or 4 with two
+      // every entry of the lane is read before any is summed; caps: 4 or 8
+      // with one atom per lane, 2 or 4 with two
       if (APL == 2 && cap == 2)
         gather_forces<APL, 2>(pw, fb_a, fsum);
       else if (APL == 2 || cap == 4)
@@ -1112,7 +1123,8 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
       if (pr.w & kPairEmpty) continue;
       const int i = pr.w & 0xff, j = (pr.w >> 8) & 0xff;
       float f[3];
-      e_lane += pair_force(L, pr, S.xs[i], S.xs[j], f);
+      const f32x4_t xi = lds_read4(lds_addr(S.xs + i)), xj = lds_read4(lds_addr(S.xs + j));
+      e_lane += pair_force(L, pr, make_float4(xi.x, xi.y, xi.z, 0.f), make_float4(xj.x, xj.y, xj.z, 0.f), f);
       if (f[0] != 0.f || f[1] != 0.f || f[2] != 0.f) {
         atomicAdd(&S.fx[i], double(f[0]));
         atomicAdd(&S.fy[i], double(f[1]));
@@ -1222,7 +1234,7 @@ DK_INLINE float eval_terms(const LaneLig<APL>& L, float q, float (&x)[APL][3], f
     const PairRec pr = pairs[pstep * p];
     if (pr.w & kPairEmpty) continue;
     const int i = pr.w & 0xff, j = (pr.w >> 8) & 0xff;
-    const float4 xi = S.xs[i], xj = S.xs[j];
+    const f32x4_t xi = lds_read4(lds_addr(S.xs + i)), xj = lds_read4(lds_addr(S.xs + j));
     const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
     const float d2 = dx * dx + dy * dy + dz * dz;
     const float d = sqrtf(d2);

@@ -310,6 +310,8 @@ static hipError_t launch_score_t(const ScoreArgs& a, int lpp, int apl, unsigned 
     hipLaunchKernelGGL((score_kernel<32, 1, MODE>), dim3(blocks), dim3(64), lds, s, a);
   else if (lpp == 64 && apl == 1)
     hipLaunchKernelGGL((score_kernel<64, 1, MODE>), dim3(blocks), dim3(64), lds, s, a);
+  else if (lpp == 32 && apl == 2)
+    hipLaunchKernelGGL((score_kernel<32, 2, MODE>), dim3(blocks), dim3(64), lds, s, a);
   else
     hipLaunchKernelGGL((score_kernel<64, 2, MODE>), dim3(blocks), dim3(64), lds, s, a);
   return hipGetLastError();
@@ -403,6 +405,8 @@ static hipError_t launch_terms_k(const TermsArgs& a, int lpp, int apl, unsigned 
     hipLaunchKernelGGL((terms_kernel<32, 1, K, XIN>), dim3(blocks), dim3(64), lds, s, a);
   else if (lpp == 64 && apl == 1)
     hipLaunchKernelGGL((terms_kernel<64, 1, K, XIN>), dim3(blocks), dim3(64), lds, s, a);
+  else if (lpp == 32 && apl == 2)
+    hipLaunchKernelGGL((terms_kernel<32, 2, K, XIN>), dim3(blocks), dim3(64), lds, s, a);
   else
     hipLaunchKernelGGL((terms_kernel<64, 2, K, XIN>), dim3(blocks), dim3(64), lds, s, a);
   return hipGetLastError();
@@ -617,9 +621,10 @@ static hipError_t launch_sample_t(const SampleArgs& a, int grid, hipStream_t s) 
   return hipGetLastError();
 }
 
-#define DOCK_SAMPLE_CASES(X)                                                        \
-  X(16, 1, 64) X(32, 1, 64) X(64, 1, 64) X(64, 2, 64) X(16, 1, 128) X(32, 1, 128) \
-      X(64, 1, 128) X(64, 2, 128) X(16, 1, 256) X(32, 1, 256) X(64, 1, 256) X(64, 2, 256)
+#define DOCK_SAMPLE_CASES(X)                                                                      \
+  X(16, 1, 64) X(32, 1, 64) X(64, 1, 64) X(32, 2, 64) X(64, 2, 64) X(16, 1, 128) X(32, 1, 128)    \
+      X(64, 1, 128) X(32, 2, 128) X(64, 2, 128) X(16, 1, 256) X(32, 1, 256) X(64, 1, 256)          \
+          X(32, 2, 256) X(64, 2, 256)
 
 hipError_t launch_sample(const SampleArgs& a, int lpp, int apl, int grid, int block, int mode,
                          hipStream_t s) {
