@@ -249,7 +249,9 @@ typedef struct {
   int32_t use_graph;        /* batched: replay the launch sequence as a hipGraph */
   int32_t steps_per_launch; /* 0: all steps in one launch per bucket */
   int32_t record_trace;     /* store q, E, dE/dq of every evaluation (tests) */
-  int32_t lanes_per_pose;   /* 0: planner choice; else 16, 32 or 64 */
+  int32_t lanes_per_pose;   /* 0: planner choice; else 16, 32 or 64: a wider group
+                               for ligands laid out one atom per lane (ligands with
+                               two atoms per lane keep their width) */
   float rms_alpha;          /* RMSprop smoothing (0.99) */
   float weight_decay;       /* AdamW decoupled weight decay (0.01) */
 } dock_sample_params;
