@@ -1067,7 +1067,13 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
     // host stages after the pull bytes) and is unused
     const uint32_t* pulls32 = reinterpret_cast<const uint32_t*>(pairs + 2 * L.n_prec);
     const uint32_t xs_a = lds_addr(S.xs), fb_a = lds_addr(S.fb);
-    if (r == 0) S.fb[W] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r == 0) {
+      // a zero produced here, not a zero tuple kept live (and spilled)
+      // across the sampler's loops
+      float z = 0.f;
+      asm volatile("" : "+v"(z));
+      *(__attribute__((address_space(3))) f32x4_t*)(uintptr_t)(fb_a + 16u * uint32_t(W)) = f32x4_t{z, z, z, z};
+    }
     // lanes without a slot hold no atom either: their gather is unused
     const int lane_slot = slot_lane ? r : 0;
     auto pull_word = [&](int ps) {
