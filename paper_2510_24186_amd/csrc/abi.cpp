@@ -84,6 +84,7 @@ struct dock_ligands_s {
   std::vector<LigandHost> host;
   std::vector<LigDev> h_ligs;
   int n = 0, max_atoms = 0, max_tors = 0, max_pairs = 0, max_frags = 0;
+  int max_alt_pairs = 0;  // largest staged alternative layout
   long long total_atoms = 0;
   bool host_only = false;
   LigDev* d_ligs = nullptr;
@@ -139,6 +140,9 @@ static void drop_tables_with(dock_pocket_t p) {
 
 // ---------------------------------------------------------------- lane plan
 
+// Wavefronts one CU holds with the sampler's register budget (3 per SIMD).
+constexpr int kWavesPerCu = 12;
+
 struct LaneCfg {
   int lpp, apl;
 };
@@ -147,9 +151,10 @@ struct LaneCfg {
 // lane up to 32 atoms; two per lane above 64, and from 33 to 64 atoms when
 // the DOFs and fragments fit 32 lanes (two poses per wavefront then share the
 // per-pose work: FK transforms, scans, optimiser updates).
-static LaneCfg lane_cfg(const LigDev& lg, int force_lpp) {
+static LaneCfg lane_cfg(const LigDev& lg, int force_lpp, bool one_per_lane = false) {
   LaneCfg c;
-  const bool mid = lg.n_atoms > 32 && lg.n_atoms <= 64 && lg.n_dof <= 32 && lg.n_frags <= 32;
+  const bool mid = !one_per_lane && lg.n_atoms > 32 && lg.n_atoms <= 64 && lg.n_dof <= 32 &&
+                   lg.n_frags <= 32;
   c.apl = (lg.n_atoms > 64 || mid) ? 2 : 1;
   const int need = std::max({(lg.n_atoms + c.apl - 1) / c.apl, lg.n_dof, lg.n_frags});
   c.lpp = need <= 16 ? 16 : (need <= 32 ? 32 : 64);
@@ -160,19 +165,16 @@ static LaneCfg lane_cfg(const LigDev& lg, int force_lpp) {
 
 // One lane configuration wide enough for every ligand of a handle (the score
 // and differentiable kernels launch one grid).
-// Each group of these kernels stages its own pose's pair records, so two
-// 32-lane groups per 64-lane block need twice the pair budget; when that
-// exceeds the LDS, one 64-lane group per block is used (ligands laid out for
-// 32-lane groups then take the strided pair path).
+// These kernels run on the ligands' alternative (one atom per lane up to 64
+// atoms) layouts: a launch holds few poses of each ligand.
 static LaneCfg wide_cfg(const dock_ligands_s* L) {
   LaneCfg w{16, 1};
   for (const LigDev& g : L->h_ligs) {
-    const LaneCfg c = lane_cfg(g, 0);
+    const LaneCfg c = lane_cfg(g, 0, true);
     w.lpp = std::max(w.lpp, c.lpp);
     w.apl = std::max(w.apl, c.apl);
   }
-  if (w.apl == 2) w.lpp = std::max(w.lpp, 32);
-  if (w.lpp < 64 && score_lds_bytes(w.lpp, w.apl, L->max_pairs) > 64 * 1024) w.lpp = 64;
+  if (w.apl == 2) w.lpp = 64;
   return w;
 }
 
@@ -596,61 +598,79 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
       std::memcpy(&u, &f, 4);
       return u;
     };
-    const LaneCfg lc = lane_cfg(g, 0);
-    PassPlan plan;
-    if (!pi_new.empty()) plan = schedule_passes(H.n_atoms, pi_new, pj_new, lc.lpp, lc.apl);
-    // the pass layout stages 2 entries per slot and apl * cap pull bytes per
-    // lane and pass; with two atoms per lane it is kept only where it fits
-    // the LDS budget
-    const size_t pull_bytes = size_t(plan.n_pass) * lc.lpp * lc.apl * plan.cap;
-    const size_t pass_entries = plan.slot_i.size() * 2 + pull_bytes / sizeof(PairRec) + 1;
-    if (plan.n_pass > 0 && (lc.apl == 1 || pass_entries * sizeof(PairRec) <= kPassStageBytes)) {
-      g.n_pass = plan.n_pass;
-      g.pass_w = lc.lpp;
-      g.pass_apl = lc.apl;
-      g.pull_cap = plan.cap;
-      // 16-byte slot records (pair word, radius sum, d_clash^2 as the device
-      // squares it, log2 d_clash), then the pull words (apl * width per pass)
-      for (size_t s = 0; s < plan.slot_i.size(); ++s) {
-        const int i0 = plan.slot_i[s], j0 = plan.slot_j[s];
-        pairs.push_back(record(i0, j0));
-        PairRec cl{};
-        if (i0 >= 0) {
-          const TypePair& tp = tab[H.type[H.dfs_atom[i0]] * kTypes + H.type[H.dfs_atom[j0]]];
-          // negated for a donor/acceptor pair: the kernel tests |d_clash^2|
-          // for the clash term and the sign for the hydrogen-bond term
-          cl.w = bits((tp.flags & 1u) ? -tp.dclash2 : tp.dclash2);
-          cl.rsum = float(std::log2(double(tp.dclash)));
-        }
-        pairs.push_back(cl);
-      }
-      // pull bytes per (pass, lane): the lane's atoms one after the other,
-      // the first `cap` bytes of each atom's pull list
-      std::vector<uint8_t> pb(pull_bytes);
-      const int per_lane = lc.apl * plan.cap;
-      for (int ps = 0; ps < plan.n_pass; ++ps)
-        for (int ln = 0; ln < lc.lpp; ++ln)
-          for (int sa = 0; sa < lc.apl; ++sa) {
-            const uint64_t w = plan.pulls[size_t(ps) * plan.n_pull + lc.apl * ln + sa];
-            for (int b = 0; b < plan.cap; ++b)
-              pb[(size_t(ps) * lc.lpp + ln) * per_lane + sa * plan.cap + b] = uint8_t(w >> (8 * b));
+    // one pair layout for a lane configuration, appended to `pairs`
+    auto emit_layout = [&](const LaneCfg& lc) {
+      PairLayout lay{};
+      lay.pair_off = int(pairs.size());
+      PassPlan plan;
+      if (!pi_new.empty()) plan = schedule_passes(H.n_atoms, pi_new, pj_new, lc.lpp, lc.apl);
+      // the pass layout stages 2 entries per slot and apl * cap pull bytes
+      // per lane and pass; with two atoms per lane above 64 atoms it is kept
+      // only where it fits the LDS budget
+      const size_t pull_bytes = size_t(plan.n_pass) * lc.lpp * lc.apl * plan.cap;
+      const size_t pass_entries = plan.slot_i.size() * 2 + pull_bytes / sizeof(PairRec) + 1;
+      if (plan.n_pass > 0 &&
+          (H.n_atoms <= 64 || pass_entries * sizeof(PairRec) <= kPassStageBytes)) {
+        lay.n_pass = plan.n_pass;
+        lay.pass_w = lc.lpp;
+        lay.pass_apl = lc.apl;
+        lay.pull_cap = plan.cap;
+        // 16-byte slot records (pair word, radius sum, d_clash^2 as the
+        // device squares it, log2 d_clash), then the pull bytes
+        for (size_t s = 0; s < plan.slot_i.size(); ++s) {
+          const int i0 = plan.slot_i[s], j0 = plan.slot_j[s];
+          pairs.push_back(record(i0, j0));
+          PairRec cl{};
+          if (i0 >= 0) {
+            const TypePair& tp = tab[H.type[H.dfs_atom[i0]] * kTypes + H.type[H.dfs_atom[j0]]];
+            // negated for a donor/acceptor pair: the kernel tests
+            // |d_clash^2| for the clash term and the sign for the
+            // hydrogen-bond term
+            cl.w = bits((tp.flags & 1u) ? -tp.dclash2 : tp.dclash2);
+            cl.rsum = float(std::log2(double(tp.dclash)));
           }
-      for (size_t o = 0; o < pb.size(); o += sizeof(PairRec)) {
-        PairRec pw;
-        std::memcpy(&pw, pb.data() + o, sizeof(PairRec));
-        pairs.push_back(pw);
+          pairs.push_back(cl);
+        }
+        // pull bytes per (pass, lane): the lane's atoms one after the other,
+        // the first `cap` bytes of each atom's pull list
+        std::vector<uint8_t> pb(pull_bytes);
+        const int per_lane = lc.apl * plan.cap;
+        for (int ps = 0; ps < plan.n_pass; ++ps)
+          for (int ln = 0; ln < lc.lpp; ++ln)
+            for (int sa = 0; sa < lc.apl; ++sa) {
+              const uint64_t w = plan.pulls[size_t(ps) * plan.n_pull + lc.apl * ln + sa];
+              for (int b = 0; b < plan.cap; ++b)
+                pb[(size_t(ps) * lc.lpp + ln) * per_lane + sa * plan.cap + b] = uint8_t(w >> (8 * b));
+            }
+        for (size_t o = 0; o < pb.size(); o += sizeof(PairRec)) {
+          PairRec pw;
+          std::memcpy(&pw, pb.data() + o, sizeof(PairRec));
+          pairs.push_back(pw);
+        }
+        // padding: the kernel reads each 4-byte pull word with its successor
+        pairs.push_back(PairRec{});
+        lay.n_prec = int(plan.slot_i.size());
+      } else {
+        for (size_t p = 0; p < pi_new.size(); ++p) pairs.push_back(record(pi_new[p], pj_new[p]));
+        lay.n_prec = int(pi_new.size());
       }
-      // padding: the kernel reads each 4-byte pull word with its successor
-      pairs.push_back(PairRec{});
-      g.n_prec = int(plan.slot_i.size());
-    } else {
-      for (size_t p = 0; p < pi_new.size(); ++p) pairs.push_back(record(pi_new[p], pj_new[p]));
-      g.n_prec = int(pi_new.size());
-    }
-    g.n_stage = int(pairs.size()) - g.pair_off;
+      lay.n_stage = int(pairs.size()) - lay.pair_off;
+      return lay;
+    };
+    const LaneCfg lc = lane_cfg(g, 0), la = lane_cfg(g, 0, true);
+    const PairLayout prim = emit_layout(lc);
+    g.pair_off = prim.pair_off;
+    g.n_prec = prim.n_prec;
+    g.n_pass = prim.n_pass;
+    g.pass_w = prim.pass_w;
+    g.pull_cap = prim.pull_cap;
+    g.pass_apl = prim.pass_apl;
+    g.alt = (la.lpp == lc.lpp && la.apl == lc.apl) ? prim : emit_layout(la);
+    g.n_stage = prim.n_stage;
     L->max_atoms = std::max(L->max_atoms, H.n_atoms);
     L->max_tors = std::max(L->max_tors, H.n_tors);
-    L->max_pairs = std::max(L->max_pairs, g.n_stage);
+    L->max_pairs = std::max({L->max_pairs, g.n_stage, g.alt.n_stage});
+    L->max_alt_pairs = std::max(L->max_alt_pairs, g.alt.n_stage);
     L->max_frags = std::max(L->max_frags, H.n_frags);
     L->total_atoms += H.n_atoms;
   }
@@ -826,7 +846,7 @@ int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligand
   if (rc) return rc;
   const LaneCfg wc = wide_cfg(L);
   const int lpp = wc.lpp, apl = wc.apl;
-  if (score_lds_bytes(lpp, apl, L->max_pairs) > 64 * 1024)
+  if (score_lds_bytes(lpp, apl, L->max_alt_pairs) > 64 * 1024)
     return fail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
   ScoreArgs a{};
   a.L = L->arrays();
@@ -841,7 +861,7 @@ int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligand
   a.dEdq = dEdq;
   a.xyz = xyz_out;
   a.xyz_stride = xyz_stride;
-  a.max_pairs = L->max_pairs;
+  a.max_pairs = L->max_alt_pairs;
   HIP_TRY(launch_score(a, lpp, apl, eval_mode(pockets, n_pockets, L),
                        reinterpret_cast<hipStream_t>(stream)));
   return DOCK_OK;
@@ -883,7 +903,7 @@ static int terms_call(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   }
   const LaneCfg wc = wide_cfg(L);
   const int lpp = wc.lpp, apl = wc.apl;
-  if (score_lds_bytes(lpp, apl, L->max_pairs) > 64 * 1024)
+  if (score_lds_bytes(lpp, apl, L->max_alt_pairs) > 64 * 1024)
     return fail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
   a.L = L->arrays();
   a.pockets = tab;
@@ -901,7 +921,7 @@ static int terms_call(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   a.dLdw = dLdw;
   a.dLdq = dLdq;
   a.dLdx = dLdx;
-  a.max_pairs = L->max_pairs;
+  a.max_pairs = L->max_alt_pairs;
   HIP_TRY(launch_terms(a, lpp, apl, K, reinterpret_cast<hipStream_t>(stream)));
   return DOCK_OK;
 }
@@ -949,6 +969,7 @@ void dock_sample_params_default(dock_sample_params* p) {
 
 struct Bucket {
   int lpp = 0, apl = 0, block = 256, max_pairs = 0;
+  int alt = 0;                     // ligands use their alternative pair layout
   int item_off = 0, n_items = 0;   // batched: this bucket's items
   int grid = 0;                    // batched: persistent grid
   std::vector<int> ligs;
@@ -1119,7 +1140,7 @@ static hipError_t enqueue_phase(dock_run_s* r, bool init, int steps, hipStream_t
         a.items = r->d_items + r->lig_item_off[l];
         a.n_items = r->lig_n_items[l];
         a.queue = nullptr;
-        a.max_pairs = r->L->h_ligs[l].n_stage;
+        a.max_pairs = B.alt ? r->L->h_ligs[l].alt.n_stage : r->L->h_ligs[l].n_stage;
         e = timed_launch(r, a, r->lig_bucket[l], B.lpp, B.apl, r->lig_n_items[l], B.block, s);
         if (e != hipSuccess) return e;
       }
@@ -1240,8 +1261,19 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   std::map<std::tuple<int, int, int>, int> bidx;
   r->lig_bucket.resize(r->n_lig);
   const std::string arch = device_arch();
+  // Two atoms per lane (ligands of 33-64 atoms) pays when the run fills the
+  // chip many times over; a smaller run keeps one atom per lane, which gives
+  // it twice the wavefronts.  The choice depends on the ligand set and the
+  // trajectory count only, so every form of the run evaluates alike.
+  long long mid_traj = 0;
   for (int l = 0; l < r->n_lig; ++l) {
-    LaneCfg c = lane_cfg(L->h_ligs[l], p->lanes_per_pose);
+    if (ov && ov->subset && !(*ov->subset)[l]) continue;
+    const LigDev& g = L->h_ligs[l];
+    if (g.n_atoms <= 64 && lane_cfg(g, 0).apl == 2) mid_traj += r->T;
+  }
+  const bool one_per_lane = mid_traj / 2 < 2LL * kWavesPerCu * n_cu;
+  for (int l = 0; l < r->n_lig; ++l) {
+    LaneCfg c = lane_cfg(L->h_ligs[l], p->lanes_per_pose, one_per_lane);
     int block = 256;
     if (ov && ov->lpp) {
       if (c.lpp == ov->nat_lpp && c.apl == ov->nat_apl) {
@@ -1263,12 +1295,16 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
       B.lpp = c.lpp;
       B.apl = c.apl;
       B.block = block;
+      // the kernels with one atom per lane read the alternative layout (the
+      // primary one for every ligand not laid out with two atoms per lane)
+      B.alt = c.apl == 1 ? 1 : 0;
       it = bidx.emplace(key, int(r->buckets.size())).first;
       r->buckets.push_back(B);
     }
     Bucket& B = r->buckets[it->second];
     B.ligs.push_back(l);
-    B.max_pairs = std::max(B.max_pairs, L->h_ligs[l].n_stage);
+    const LigDev& gl = L->h_ligs[l];
+    B.max_pairs = std::max(B.max_pairs, B.alt ? gl.alt.n_stage : gl.n_stage);
     r->lig_bucket[l] = it->second;
   }
   std::vector<int2> items;
@@ -1291,7 +1327,8 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
       std::vector<int> ligs = B.ligs;
       const auto cost = [&](int l) {
         const LigDev& g = L->h_ligs[l];
-        return (g.n_pass > 0 ? g.n_prec : g.n_pairs) + 4 * g.n_atoms;
+        const int n_pass = B.alt ? g.alt.n_pass : g.n_pass, n_prec = B.alt ? g.alt.n_prec : g.n_prec;
+        return (n_pass > 0 ? n_prec : g.n_pairs) + 4 * g.n_atoms;
       };
       std::stable_sort(ligs.begin(), ligs.end(), [&](int x, int y) { return cost(x) > cost(y); });
       B.item_off = int(items.size());

@@ -17,6 +17,14 @@ constexpr int kMaxTors = DOCK_MAX_TORS;
 constexpr int kMaxDof = 6 + DOCK_MAX_TORS;
 constexpr int kMaxTerms = DOCK_MAX_TERMS;
 
+// Where one layout of a ligand's pair records sits in the packed array, and
+// its shape (see LigDev).
+struct PairLayout {
+  int pair_off, n_prec, n_stage;
+  int n_pass, pass_w, pull_cap, pass_apl;
+  int pad;
+};
+
 // Per-ligand record, device resident.  Atoms are stored in fragment
 // depth-first pre-order so that every torsion's moving subtree is one
 // contiguous atom range (the chain rule sums over ranges).
@@ -30,7 +38,24 @@ struct alignas(16) LigDev {
   int n_pass, pass_w, pull_cap;           // pass layout (n_pass = 0: pairs are strided, forces by atomics)
   int pass_apl;                           // atoms per lane of the pass layout (pull words per pass = apl * w)
   int n_stage;                            // 8-byte entries to stage: pair records (+ pull words)
+  // The fields above describe the primary pair layout (the lane
+  // configuration of large batched runs).  `alt` is the layout with one atom
+  // per lane up to 64 atoms, for launches that hold few poses of a ligand
+  // (plain form, the single-launch kernels, small batches); it equals the
+  // primary one where that already has one atom per lane.
+  PairLayout alt;
 };
+
+// Switches a copy of a ligand record to its alternative pair layout.
+__host__ __device__ inline void use_alt_layout(LigDev& g) {
+  g.pair_off = g.alt.pair_off;
+  g.n_prec = g.alt.n_prec;
+  g.n_stage = g.alt.n_stage;
+  g.n_pass = g.alt.n_pass;
+  g.pass_w = g.alt.pass_w;
+  g.pull_cap = g.alt.pull_cap;
+  g.pass_apl = g.alt.pass_apl;
+}
 
 // Fragment record (DFS numbering).  Root: parent = -1, dof = -1.
 // A child turns about the input-frame axis through xb with unit direction u.

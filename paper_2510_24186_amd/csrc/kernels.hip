@@ -276,7 +276,10 @@ __global__ void __launch_bounds__(64) score_kernel(ScoreArgs a) {
     if (r == 0) a.E[pose] = __int_as_float(0x7fc00000);
     return;
   }
-  const LigDev lg = a.L.ligs[lig];
+  // single-launch kernels use the alternative (one atom per lane up to 64
+  // atoms) pair layouts
+  LigDev lg = a.L.ligs[lig];
+  use_alt_layout(lg);
   const PocketDev pk = a.pockets[lg.pocket];
   LaneLig<APL> L;
   load_lane_lig<LPP, APL>(L, lg, a.L.ligs + lig, a.L.atoms, a.L.frags, a.L.tors, pk, r);
@@ -310,8 +313,6 @@ static hipError_t launch_score_t(const ScoreArgs& a, int lpp, int apl, unsigned 
     hipLaunchKernelGGL((score_kernel<32, 1, MODE>), dim3(blocks), dim3(64), lds, s, a);
   else if (lpp == 64 && apl == 1)
     hipLaunchKernelGGL((score_kernel<64, 1, MODE>), dim3(blocks), dim3(64), lds, s, a);
-  else if (lpp == 32 && apl == 2)
-    hipLaunchKernelGGL((score_kernel<32, 2, MODE>), dim3(blocks), dim3(64), lds, s, a);
   else
     hipLaunchKernelGGL((score_kernel<64, 2, MODE>), dim3(blocks), dim3(64), lds, s, a);
   return hipGetLastError();
@@ -344,7 +345,8 @@ __global__ void __launch_bounds__(64) terms_kernel(TermsArgs a) {
     if (r == 0 && a.E) a.E[pose] = __int_as_float(0x7fc00000);
     return;
   }
-  const LigDev lg = a.L.ligs[lig];
+  LigDev lg = a.L.ligs[lig];
+  use_alt_layout(lg);
   const int pi = lg.pocket;
   const PocketDev pk = a.pockets[pi];
   LaneLig<APL> L;
@@ -405,8 +407,6 @@ static hipError_t launch_terms_k(const TermsArgs& a, int lpp, int apl, unsigned 
     hipLaunchKernelGGL((terms_kernel<32, 1, K, XIN>), dim3(blocks), dim3(64), lds, s, a);
   else if (lpp == 64 && apl == 1)
     hipLaunchKernelGGL((terms_kernel<64, 1, K, XIN>), dim3(blocks), dim3(64), lds, s, a);
-  else if (lpp == 32 && apl == 2)
-    hipLaunchKernelGGL((terms_kernel<32, 2, K, XIN>), dim3(blocks), dim3(64), lds, s, a);
   else
     hipLaunchKernelGGL((terms_kernel<64, 2, K, XIN>), dim3(blocks), dim3(64), lds, s, a);
   return hipGetLastError();
@@ -600,7 +600,10 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
     ++taken;
     const int2 wi = a.items[item];
     const int lig = wi.x;
-    const LigDev lg = a.L.ligs[lig];
+    // one atom per lane: the alternative layout (the primary one for every
+    // ligand not laid out with two atoms per lane)
+    LigDev lg = a.L.ligs[lig];
+    if (APL == 1) use_alt_layout(lg);
     for (int p = threadIdx.x; p < lg.n_stage; p += BLOCK) sp[p] = a.L.pairs[lg.pair_off + p];
     __syncthreads();
     const int traj = wi.y + grp;

@@ -3,6 +3,8 @@ distributions.  Run on an MI355X.
 
 * plain, batched, hipGraph-replayed and chunked launches give bit-identical
   trajectories (random streams depend on ligand, trajectory and step only);
+* a run large enough for two atoms per lane (33-64-atom ligands) uses that
+  layout, its logged evaluations match the oracle and its forms agree;
 * run(S) == run(s) + advance(S - s) == restore(state at s) + advance, bitwise;
 * the recorded trace is self-consistent (score kernel at the logged q, Adam
   update rule between consecutive rows, Armijo condition for line search);
@@ -80,6 +82,61 @@ def test_forced_wider_groups_agree(D, mixed):
     b = _state(D, D.dock_sample(p, H, lanes_per_pose=64, **kw))
     # different reduction trees: close, not bitwise
     np.testing.assert_allclose(a["E_cur"][:, :], b["E_cur"], rtol=2e-3, atol=1e-3)
+
+
+def _two_per_lane_traj(mid):
+    """Trajectories per ligand at which a run lays out the 33-64-atom ligands
+    two atoms per lane: two poses per wavefront must fill at least two waves
+    per wave slot (12 waves per CU)."""
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    need = 2 * 2 * 12 * n_cu
+    return 64 * (-(-need // (64 * mid)) + 1)
+
+
+def test_two_atoms_per_lane_runs_against_oracle(D, mixed):
+    """A run that fills the chip with two poses per wavefront lays out the
+    33-64-atom ligands two atoms per lane in 32-lane groups; a small run keeps
+    one atom per lane.  The large run's logged evaluations match the oracle
+    at sampled rows, and its plain and batched forms agree bitwise."""
+    p, H, L, pk = mixed
+    topos = [topology.from_ligands(L, i) for i in range(L.n_ligands)]
+    mid = [i for i, t in enumerate(topos) if 32 < t.n_atoms <= 64 and t.n_dof <= 32]
+    assert len(mid) == 5
+    T = _two_per_lane_traj(len(mid))
+    kw = dict(n_steps=2, n_local=3, seed=21)
+    G.say("two per lane: plans, T =", T)
+    small = D.dock_sample(p, H, n_traj=16, **kw)
+    big = D.dock_sample(p, H, n_traj=T, record_trace=1, **kw)
+    for run, want in ((small, (64, 1)), (big, (32, 2))):
+        plan = D.dock_run_plan(run)
+        for i in mid:
+            b = plan["lig_bucket"][i]
+            assert (plan["lanes"][b], plan["apl"][b]) == want, (i, plan)
+    st = D.dock_run_state(big, trace=True)
+    torch.cuda.synchronize()
+    tr = st["trace"].cpu().numpy()
+    qs = st["q_stride"]
+    nev = st["n_evals"].cpu().numpy()
+    assert np.all(nev == 1 + 2 * 4)
+    sc = SC.LazyScorer(pk, P.PRESET_TRIDS, weights=G.weights32(P.PRESET_TRIDS).astype(np.float64))
+    rng = np.random.default_rng(8)
+    checked = 0
+    for i in mid:
+        t = topos[i]
+        rows = tr[i].reshape(-1, 2 * qs + 1)
+        pick = rng.choice(len(rows), 48, replace=False)
+        ref = sc.score(t, rows[pick, :t.n_dof].astype(np.float64))
+        c, _, we, wg = G.compare_eval(rows[pick, 2 * qs], rows[pick, qs:2 * qs], ref, t.n_dof,
+                                      "two per lane lig %d" % i)
+        checked += c
+        G.say("lig", i, "N", t.n_atoms, "worst E/tol %.3g g/tol %.3g" % (we, wg))
+    assert checked >= 0.9 * 48 * len(mid)
+    G.say("two per lane: forms")
+    a = _state(D, D.dock_sample(p, H, n_traj=T, form=D.FORM_PLAIN, use_graph=0, **kw))
+    b = _state(D, D.dock_sample(p, H, n_traj=T, form=D.FORM_BATCHED, use_graph=0, **kw))
+    _same(a, b, "two per lane plain/batched")
+    for k in ("q_cur", "E_cur", "q_best", "E_best"):
+        assert np.array_equal(a[k], st[k].cpu().numpy()), k
 
 
 def test_resume_and_restore_bitwise(D, mixed):
