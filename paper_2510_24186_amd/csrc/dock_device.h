@@ -179,6 +179,16 @@ DK_INLINE uint32_t lds_entry16(uint32_t packed, uint32_t base) {
 DK_INLINE f32x4_t lds_read4(uint32_t a) {
   return *(const volatile __attribute__((address_space(3))) f32x4_t*)(uintptr_t)a;
 }
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+DK_INLINE uint4 lds_read_u4(uint32_t a) {
+  const u32x4_t v = *(const __attribute__((address_space(3))) u32x4_t*)(uintptr_t)a;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+// two consecutive dwords at a 4-byte aligned address (one ds_read2_b32)
+DK_INLINE uint2 lds_read_u2(uint32_t a) {
+  const __attribute__((address_space(3))) uint32_t* p = (const __attribute__((address_space(3))) uint32_t*)(uintptr_t)a;
+  return make_uint2(p[0], p[1]);
+}
 DK_INLINE void lds_write4(uint32_t a, float x, float y, float z) {
   const f32x4_t v = {x, y, z, 0.f};
   *(__attribute__((address_space(3))) f32x4_t*)(uintptr_t)a = v;
@@ -972,7 +982,7 @@ DK_INLINE float pair_force_slot(const LaneLig<APL>& L, const uint4& rp, const f3
 // CAP 8: x then y; CAP 4: atom s in word s; CAP 2: atom s in bytes 2s, 2s+1.
 template <int APL, int CAP>
 DK_INLINE void gather_forces(const uint2& pw, uint32_t fb_a, float (&fsum)[APL][3]) {
-  f32x4_t v[APL][CAP];
+  uint32_t ad[APL][CAP];
 #pragma unroll
   for (int s = 0; s < APL; ++s)
 #pragma unroll
@@ -989,8 +999,18 @@ DK_INLINE void gather_forces(const uint2& pw, uint32_t fb_a, float (&fsum)[APL][
         word = pw.x;
         k = 2 * s + c;
       }
-      v[s][c] = lds_read4(lds_entry16_k(word, k, fb_a));
+      ad[s][c] = lds_entry16_k(word, k, fb_a);
     }
+  // all addresses first: no VALU-to-LDS-address wait states between reads
+  __builtin_amdgcn_sched_barrier(0);
+  f32x4_t v[APL][CAP];
+#pragma unroll
+  for (int s = 0; s < APL; ++s)
+#pragma unroll
+    for (int c = 0; c < CAP; ++c) v[s][c] = lds_read4(ad[s][c]);
+  // keeps the scheduler from pulling the sums up between the reads (each
+  // would then wait for the read just issued)
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int s = 0; s < APL; ++s)
 #pragma unroll
@@ -1057,15 +1077,11 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
     // result does not depend on timing.
     const int W = L.pass_w;
     const bool slot_lane = r < W;
-    const uint4* recs = reinterpret_cast<const uint4*>(pairs);
     // pull bytes: APL * cap per lane and pass (4 or 8), the lane's atoms one
-    // after the other, read as one 4- or 8-byte word
+    // after the other.  Two consecutive dwords are always read (one
+    // ds_read2_b32); with 4 bytes the second belongs to the next lane (or the
+    // padding entry the host stages after the pull bytes) and is unused.
     const int cap = L.pull_cap;
-    const int wshift = APL * cap > 4 ? 1 : 0;
-    // two consecutive dwords are always read (one ds_read2_b32); with 4-byte
-    // words the second belongs to the next lane (or the padding entry the
-    // host stages after the pull bytes) and is unused
-    const uint32_t* pulls32 = reinterpret_cast<const uint32_t*>(pairs + 2 * L.n_prec);
     const uint32_t xs_a = lds_addr(S.xs), fb_a = lds_addr(S.fb);
     if (r == 0) {
       // a zero produced here, not a zero tuple kept live (and spilled)
@@ -1075,40 +1091,49 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
       *(__attribute__((address_space(3))) f32x4_t*)(uintptr_t)(fb_a + 16u * uint32_t(W)) = f32x4_t{z, z, z, z};
     }
     // lanes without a slot hold no atom either: their gather is unused
-    const int lane_slot = slot_lane ? r : 0;
-    auto pull_word = [&](int ps) {
-      const int j = (ps * W + lane_slot) << wshift;
-      return make_uint2(pulls32[j], pulls32[j + 1]);
-    };
-    // the next pass's record and pull word are read before this pass's
-    // gather, so their latency overlaps the gather and the sums
-    uint4 rp_next = recs[lane_slot];
-    uint2 pw_next = pull_word(0);
-    for (int ps = 0; ps < L.n_pass; ++ps) {
-      const uint4 rp = rp_next;
-      const uint2 pw = pw_next;
-      const f32x4_t xi = lds_read4(lds_entry16<0>(rp.x, xs_a));
-      const f32x4_t xj = lds_read4(lds_entry16<1>(rp.x, xs_a));
-      float f[3];
-      const float e = pair_force_slot(L, rp, xi, xj, f);
-      if (slot_lane) {
-        e_lane += e;
-        lds_write4(fb_a + 16u * uint32_t(r), f[0], f[1], f[2]);
+    const uint32_t lane_slot = slot_lane ? uint32_t(r) : 0u;
+    const uint32_t recs_a = lds_addr(pairs), pulls_a = recs_a + 16u * uint32_t(L.n_prec);
+    // one loop per cap, so the gather's results stay in the same registers
+    // from pass to pass
+    auto run_passes = [&](auto cap_c) {
+      constexpr int CAP = decltype(cap_c)::value;
+      constexpr uint32_t kPullBytes = APL * CAP;
+      // this lane's record and pull word of the next pass, read before this
+      // pass's gather so that their latency overlaps the gather and the sums
+      uint32_t rec_a = recs_a + 16u * lane_slot, pw_a = pulls_a + kPullBytes * lane_slot;
+      const uint32_t rec_step = 16u * uint32_t(W), pw_step = kPullBytes * uint32_t(W);
+      uint4 rp_next = lds_read_u4(rec_a);
+      uint2 pw_next = lds_read_u2(pw_a);
+      for (int ps = 0; ps < L.n_pass; ++ps) {
+        const uint4 rp = rp_next;
+        const uint2 pw = pw_next;
+        const f32x4_t xi = lds_read4(lds_entry16<0>(rp.x, xs_a));
+        const f32x4_t xj = lds_read4(lds_entry16<1>(rp.x, xs_a));
+        float f[3];
+        const float e = pair_force_slot(L, rp, xi, xj, f);
+        if (slot_lane) {
+          e_lane += e;
+          lds_write4(fb_a + 16u * uint32_t(r), f[0], f[1], f[2]);
+        }
+        if (ps + 1 < L.n_pass) {
+          rec_a += rec_step;
+          pw_a += pw_step;
+        }
+        rp_next = lds_read_u4(rec_a);
+        pw_next = lds_read_u2(pw_a);
+        wave_sync();
+        // every entry of the lane is read before any is summed
+        gather_forces<APL, CAP>(pw, fb_a, fsum);
+        wave_sync();
       }
-      const int next = ps + 1 < L.n_pass ? ps + 1 : ps;
-      rp_next = recs[next * W + lane_slot];
-      pw_next = pull_word(next);
-      wave_sync();
-      // every entry of the lane is read before any is summed; caps: 4 or 8
-      // with one atom per lane, 2 or 4 with two
-      if (APL == 2 && cap == 2)
-        gather_forces<APL, 2>(pw, fb_a, fsum);
-      else if (APL == 2 || cap == 4)
-        gather_forces<APL, 4>(pw, fb_a, fsum);
-      else
-        gather_forces<APL, 8>(pw, fb_a, fsum);
-      wave_sync();
-    }
+    };
+    // caps: 4 or 8 with one atom per lane, 2 or 4 with two
+    if (APL == 2 && cap == 2)
+      run_passes(std::integral_constant<int, 2>{});
+    else if (APL == 2 || cap == 4)
+      run_passes(std::integral_constant<int, 4>{});
+    else
+      run_passes(std::integral_constant<int, 8>{});
   } else {
     // ---- strided: lane r takes records r, r + LPP, ...; forces by LDS atomics
 #pragma unroll
