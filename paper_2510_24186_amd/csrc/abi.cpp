@@ -1008,11 +1008,38 @@ struct dock_run_s {
   bool recording = false;
   // batched form with several buckets: bucket b > 0 runs on side[b - 1],
   // forked from and joined back into the caller's stream, so a bucket too
-  // small to fill the chip and the tail of a large one overlap
+  // small to fill the chip and the tail of a large one overlap.  The side
+  // streams belong to the device's process-wide pool (side_streams).
   std::vector<hipStream_t> side;
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
 };
+
+// Side streams of the batched form, shared by every run on a device and kept
+// until the process ends.  The runtime hands each new stream a hardware
+// queue; streams created and destroyed with each run were at times handed the
+// queue of the caller's stream (or of another side stream), and the buckets
+// on it then ran one after the other.  Created once, the pool's streams keep
+// their queues.  Runs enqueued from several host threads at once share these
+// streams: eager launches stay ordered by the fork and join events, but
+// capturing graphs from several threads at once is not supported.
+static int side_streams(size_t n, std::vector<hipStream_t>* out) {
+  static std::mutex mu;
+  static std::map<int, std::vector<hipStream_t>> pool;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(DOCK_E_HIP, std::string("bucket streams: ") + hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(mu);
+  std::vector<hipStream_t>& v = pool[dev];
+  while (v.size() < n) {
+    hipStream_t q = nullptr;
+    e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(DOCK_E_HIP, std::string("bucket streams: ") + hipGetErrorString(e));
+    v.push_back(q);
+  }
+  out->assign(v.begin(), v.begin() + n);
+  return DOCK_OK;
+}
 
 static hipEvent_t pool_event(dock_run_s* r) {
   if (r->events_used == r->event_pool.size()) {
@@ -1055,7 +1082,6 @@ static hipError_t timed_launch(dock_run_s* r, const SampleArgs& a, int bucket, i
 static void free_run(dock_run_s* r) {
   for (hipEvent_t e : r->event_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : r->join) (void)hipEventDestroy(e);
-  for (hipStream_t q : r->side) (void)hipStreamDestroy(q);
   if (r->fork) (void)hipEventDestroy(r->fork);
   if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
   if (r->graph) (void)hipGraphDestroy(r->graph);
@@ -1347,16 +1373,17 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
     if (sample_lds_bytes(B.lpp, B.apl, B.block, B.max_pairs) > 64 * 1024)
       return bail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
   if (p->form == DOCK_FORM_BATCHED && r->buckets.size() > 1) {
+    if (side_streams(r->buckets.size() - 1, &r->side) != DOCK_OK) {
+      const std::string m = g_err;
+      return bail(DOCK_E_HIP, m);
+    }
     hipError_t se = hipEventCreateWithFlags(&r->fork, hipEventDisableTiming);
     for (size_t b = 1; b < r->buckets.size() && se == hipSuccess; ++b) {
-      hipStream_t q = nullptr;
       hipEvent_t j = nullptr;
-      se = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
-      if (se == hipSuccess) r->side.push_back(q);
-      if (se == hipSuccess) se = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+      se = hipEventCreateWithFlags(&j, hipEventDisableTiming);
       if (se == hipSuccess) r->join.push_back(j);
     }
-    if (se != hipSuccess) return bail(DOCK_E_HIP, std::string("bucket streams: ") + hipGetErrorString(se));
+    if (se != hipSuccess) return bail(DOCK_E_HIP, std::string("bucket events: ") + hipGetErrorString(se));
   }
   // ---- buffers
   const size_t nt = size_t(r->n_lig) * r->T;

@@ -980,8 +980,10 @@ DK_INLINE float pair_force_slot(const LaneLig<APL>& L, const uint4& rp, const f3
 // first CAP/2 added and the rest subtracted, all reads issued before the
 // first sum.  The lane's pull bytes (APL * CAP of them) are packed in pw:
 // CAP 8: x then y; CAP 4: atom s in word s; CAP 2: atom s in bytes 2s, 2s+1.
-template <int APL, int CAP>
-DK_INLINE void gather_forces(const uint2& pw, uint32_t fb_a, float (&fsum)[APL][3]) {
+// `between` runs after the reads are issued and before the sums (the next
+// pass's position reads go there, so their latency overlaps the sums).
+template <int APL, int CAP, class Between>
+DK_INLINE void gather_forces(const uint2& pw, uint32_t fb_a, float (&fsum)[APL][3], Between&& between) {
   uint32_t ad[APL][CAP];
 #pragma unroll
   for (int s = 0; s < APL; ++s)
@@ -1008,6 +1010,7 @@ DK_INLINE void gather_forces(const uint2& pw, uint32_t fb_a, float (&fsum)[APL][
   for (int s = 0; s < APL; ++s)
 #pragma unroll
     for (int c = 0; c < CAP; ++c) v[s][c] = lds_read4(ad[s][c]);
+  between();
   // keeps the scheduler from pulling the sums up between the reads (each
   // would then wait for the read just issued)
   __builtin_amdgcn_sched_barrier(0);
@@ -1098,17 +1101,16 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
     auto run_passes = [&](auto cap_c) {
       constexpr int CAP = decltype(cap_c)::value;
       constexpr uint32_t kPullBytes = APL * CAP;
-      // this lane's record and pull word of the next pass, read before this
-      // pass's gather so that their latency overlaps the gather and the sums
+      // this lane's record and pull word of the next pass are read before
+      // this pass's gather, and the record's two positions during it, so
+      // that their latency overlaps the gather and the sums
       uint32_t rec_a = recs_a + 16u * lane_slot, pw_a = pulls_a + kPullBytes * lane_slot;
       const uint32_t rec_step = 16u * uint32_t(W), pw_step = kPullBytes * uint32_t(W);
-      uint4 rp_next = lds_read_u4(rec_a);
-      uint2 pw_next = lds_read_u2(pw_a);
+      uint4 rp = lds_read_u4(rec_a);
+      uint2 pw = lds_read_u2(pw_a);
+      f32x4_t xi = lds_read4(lds_entry16<0>(rp.x, xs_a));
+      f32x4_t xj = lds_read4(lds_entry16<1>(rp.x, xs_a));
       for (int ps = 0; ps < L.n_pass; ++ps) {
-        const uint4 rp = rp_next;
-        const uint2 pw = pw_next;
-        const f32x4_t xi = lds_read4(lds_entry16<0>(rp.x, xs_a));
-        const f32x4_t xj = lds_read4(lds_entry16<1>(rp.x, xs_a));
         float f[3];
         const float e = pair_force_slot(L, rp, xi, xj, f);
         if (slot_lane) {
@@ -1119,11 +1121,17 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
           rec_a += rec_step;
           pw_a += pw_step;
         }
-        rp_next = lds_read_u4(rec_a);
-        pw_next = lds_read_u2(pw_a);
+        const uint4 rp_next = lds_read_u4(rec_a);
+        const uint2 pw_next = lds_read_u2(pw_a);
         wave_sync();
         // every entry of the lane is read before any is summed
-        gather_forces<APL, CAP>(pw, fb_a, fsum);
+        gather_forces<APL, CAP>(pw, fb_a, fsum, [&] {
+          const uint32_t ai = lds_entry16<0>(rp_next.x, xs_a), aj = lds_entry16<1>(rp_next.x, xs_a);
+          xi = lds_read4(ai);
+          xj = lds_read4(aj);
+        });
+        rp = rp_next;
+        pw = pw_next;
         wave_sync();
       }
     };
