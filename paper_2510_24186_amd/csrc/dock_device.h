@@ -1111,6 +1111,10 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
       f32x4_t xi = lds_read4(lds_entry16<0>(rp.x, xs_a));
       f32x4_t xj = lds_read4(lds_entry16<1>(rp.x, xs_a));
       for (int ps = 0; ps < L.n_pass; ++ps) {
+        // the unused 4th components stay live until here: otherwise their
+        // registers are reused for the gather's sums, which must then wait
+        // for these reads to land
+        asm volatile("" ::"v"(xi.w), "v"(xj.w));
         float f[3];
         const float e = pair_force_slot(L, rp, xi, xj, f);
         if (slot_lane) {
