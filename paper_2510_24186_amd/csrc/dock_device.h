@@ -1023,6 +1023,12 @@ DK_INLINE void gather_forces(const uint2& pw, uint32_t fb_a, float (&fsum)[APL][
       fsum[s][1] += sg * v[s][c].y;
       fsum[s][2] += sg * v[s][c].z;
     }
+  // the unused 4th components stay live through the sums (their registers
+  // would otherwise be reused there, each use waiting for its read)
+#pragma unroll
+  for (int s = 0; s < APL; ++s)
+#pragma unroll
+    for (int c = 0; c < CAP; ++c) asm volatile("" ::"v"(v[s][c].w));
 }
 
 // One evaluation of E and dE/dq at the pose whose DOF r is held by lane r.
