@@ -302,7 +302,8 @@ typedef struct {
 
 int dock_run_view_get(dock_run_t r, dock_run_view* v);
 /* Copies the run's state into caller device buffers laid out as in
- * dock_run_view (each nullable) on `stream`. */
+ * dock_run_view (each nullable) on `stream`.  Pose slots past a ligand's
+ * n_dof are zero (or what dock_run_set_state last put there). */
 int dock_run_copy_state(dock_run_t r, float* q_cur, float* E_cur, float* q_best, float* E_best,
                         int32_t* n_evals, float* trace, void* stream);
 /* Replaces the trajectory state (checkpoint restore).  Device inputs laid out

@@ -1403,6 +1403,11 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
     e = dev_alloc(&r->trace, nt * size_t(r->trace_cap) * (2 * r->q_stride + 1));
   }
   if (e != hipSuccess) return bail(DOCK_E_OOM, std::string("run allocation: ") + hipGetErrorString(e));
+  // the kernels write the n_dof leading slots of every pose row; the padding
+  // slots up to q_stride read back as zeros
+  e = hipMemsetAsync(r->q_cur, 0, sizeof(float) * nt * r->q_stride, s);
+  if (e == hipSuccess) e = hipMemsetAsync(r->q_best, 0, sizeof(float) * nt * r->q_stride, s);
+  if (e != hipSuccess) return bail(DOCK_E_HIP, std::string("run state clear: ") + hipGetErrorString(e));
   e = hipMemcpy(r->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(DOCK_E_HIP, std::string("item upload: ") + hipGetErrorString(e));
   if ((e = hipEventCreate(&r->ev0)) != hipSuccess || (e = hipEventCreate(&r->ev1)) != hipSuccess)

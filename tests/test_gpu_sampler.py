@@ -6,6 +6,8 @@ distributions.  Run on an MI355X.
 * a run large enough for two atoms per lane (33-64-atom ligands) uses that
   layout, its logged evaluations match the oracle and its forms agree;
 * run(S) == run(s) + advance(S - s) == restore(state at s) + advance, bitwise;
+* live runs sharing the device's bucket streams (interleaved advances, two
+  caller streams) reach the states each reaches alone;
 * the recorded trace is self-consistent (score kernel at the logged q, Adam
   update rule between consecutive rows, Armijo condition for line search);
 * best poses (rank, RMSD clustering, top N, E_screen) against the oracle on
@@ -137,6 +139,34 @@ def test_two_atoms_per_lane_runs_against_oracle(D, mixed):
     _same(a, b, "two per lane plain/batched")
     for k in ("q_cur", "E_cur", "q_best", "E_best"):
         assert np.array_equal(a[k], st[k].cpu().numpy()), k
+
+
+def test_live_runs_share_bucket_streams(D, mixed):
+    """Batched runs share their device's pool of bucket streams.  Two live
+    runs advanced in interleaved order, and two runs enqueued on different
+    streams without a synchronisation between them, reach the states each
+    run reaches alone."""
+    p, H, L, _ = mixed
+    kw = dict(n_traj=16, n_local=3, form=D.FORM_BATCHED)
+    G.say("shared streams: references")
+    ref_a = _state(D, D.dock_sample(p, H, n_steps=6, seed=31, **kw))
+    ref_b = _state(D, D.dock_sample(p, H, n_steps=5, seed=32, **kw))
+    assert len(D.dock_run_plan(D.dock_sample(p, H, n_steps=0, seed=31, **kw))["lanes"]) > 1
+    G.say("shared streams: interleaved advances")
+    a = D.dock_sample(p, H, n_steps=2, seed=31, **kw)
+    b = D.dock_sample(p, H, n_steps=2, seed=32, **kw)
+    D.dock_run_advance(a, 3)
+    D.dock_run_advance(b, 3)
+    D.dock_run_advance(a, 1)
+    _same(ref_a, _state(D, a), "interleaved a")
+    _same(ref_b, _state(D, b), "interleaved b")
+    G.say("shared streams: two caller streams")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ra = D.dock_sample(p, H, n_steps=6, seed=31, stream=s1, **kw)
+    rb = D.dock_sample(p, H, n_steps=5, seed=32, stream=s2, **kw)
+    torch.cuda.synchronize()
+    _same(ref_a, _state(D, ra), "stream a")
+    _same(ref_b, _state(D, rb), "stream b")
 
 
 def test_resume_and_restore_bitwise(D, mixed):
