@@ -29,9 +29,9 @@ sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
 
-# FP32 vector peak this build can reach: 256 CUs x 4 SIMDs x 16 lanes x 2
+# FP32 vector peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2
 # flops (FMA) x 2.4 GHz.  MI355X's published 157.3 TFLOP/s counts packed FP32,
-# which the build disables.
+# which the library is compiled without.
 PEAK_FP32_TFLOPS = 78.6
 PEAK_FP32_PACKED_TFLOPS = 157.3
 N_LOCAL = 10
@@ -200,8 +200,9 @@ def main():
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (every MI355X box here "
-              "has one GPU); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the sampler has no multi-GPU path (ligands and "
+              "trajectories shard across GPUs with no communication); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
