@@ -96,13 +96,17 @@ def first_order_refine(kind, score_fn, q, n_local, box_min, box_max, lr=P.ADAM_L
     return q, E
 
 
-def linesearch_refine(score_fn, q, n_local, box_min, box_max, n_evals=None):
+def linesearch_refine(score_fn, q, n_local, box_min, box_max, n_evals=None, log=None):
     """n_local Armijo steps; returns (q, E).  n_evals[p] counts evaluations.
 
     A search that finds no acceptable alpha ends the pose's refinement.
+    log(q, E, g, live), when given, receives every evaluation together with
+    the mask of poses whose search it belongs to (a record, no arithmetic).
     """
     q = np.array(q, np.float64, copy=True)
     E, g = score_fn(q)
+    if log is not None:
+        log(q, E, g, np.ones(len(q), bool))
     if n_evals is not None:
         n_evals += 1
     stopped = np.zeros(len(q), bool)
@@ -119,6 +123,8 @@ def linesearch_refine(score_fn, q, n_local, box_min, box_max, n_evals=None):
                 break
             cand = wrap_clamp(q + alpha * d, box_min, box_max)
             Ec, gc = score_fn(cand)
+            if log is not None:
+                log(cand, Ec, gc, ~done)
             if n_evals is not None:
                 n_evals += ~done
             ok = (~done) & (Ec <= E + ARMIJO_C * alpha * slope)

@@ -79,23 +79,52 @@ def initial_q(topo, lig_id, seed, traj):
     return q
 
 
-def init_state(scorer, topo, lig_id, prm, traj=None):
+class EvalLog:
+    """Every evaluation of every trajectory, in the order the trajectory makes
+    them: rows[p] is a list of (q, E, dE/dq, S_abs, margin_E, margin) with the
+    scale and margins of score.Scorer.  A record only: the sampler's
+    arithmetic does not depend on it."""
+
+    def __init__(self, n_traj):
+        self.rows = [[] for _ in range(n_traj)]
+
+    def add(self, q, r, live=None):
+        for p in range(len(q)):
+            if live is None or live[p]:
+                self.rows[p].append((q[p].copy(), float(r["E"][p]), r["dEdq"][p].copy(),
+                                     float(r["S_abs"][p]), float(r["margin_E"][p]),
+                                     float(r["margin"][p])))
+
+
+def init_state(scorer, topo, lig_id, prm, traj=None, evlog=None):
     traj = np.arange(prm.n_traj) if traj is None else np.asarray(traj)
     q = initial_q(topo, lig_id, prm.seed, traj)
-    E = scorer.energy(topo, q)
+    r = scorer.score(topo, q)
+    if evlog is not None:
+        evlog.add(q, r)
+    E = r["E"]
     return State(q_cur=q, E_cur=E, q_best=q.copy(), E_best=E.copy(), step=0)
 
 
 def run_steps(scorer, topo, lig_id, prm, state, n_steps, traj=None, trace=None,
-              n_evals=None):
-    """Advance every trajectory by n_steps MC steps (in place; returns state)."""
+              n_evals=None, evlog=None):
+    """Advance every trajectory by n_steps MC steps (in place; returns state).
+    evlog (an EvalLog) records every evaluation when given."""
     traj = np.arange(len(state.E_cur)) if traj is None else np.asarray(traj)
     lo, hi = dof_range(topo)
     n = topo.n_dof
+    last = {}
 
     def score_fn(q):
         r = scorer.score(topo, q)
+        last["r"] = r
+        if evlog is not None and prm.local_opt != LOCAL_LINESEARCH:
+            evlog.add(q, r)
         return r["E"], r["dEdq"]
+
+    def ls_log(q, E, g, live):
+        if evlog is not None:
+            evlog.add(q, last["r"], live)
 
     for _ in range(n_steps):
         s = state.step + 1
@@ -109,7 +138,7 @@ def run_steps(scorer, topo, lig_id, prm, state, n_steps, traj=None, trace=None,
                                      prm.lr, prm.beta1, prm.beta2, prm.eps)
         elif prm.local_opt == LOCAL_LINESEARCH:
             q, E = optim.linesearch_refine(score_fn, q, prm.n_local, topo.box_min,
-                                           topo.box_max, n_evals=n_evals)
+                                           topo.box_max, n_evals=n_evals, log=ls_log)
         else:
             q, E = optim.first_order_refine(prm.local_opt, score_fn, q, prm.n_local, topo.box_min,
                                             topo.box_max, prm.lr, prm.beta1, prm.beta2, prm.eps)
@@ -130,6 +159,6 @@ def run_steps(scorer, topo, lig_id, prm, state, n_steps, traj=None, trace=None,
     return state
 
 
-def sample(scorer, topo, lig_id, prm, traj=None, trace=None):
-    st = init_state(scorer, topo, lig_id, prm, traj)
-    return run_steps(scorer, topo, lig_id, prm, st, prm.n_steps, traj, trace)
+def sample(scorer, topo, lig_id, prm, traj=None, trace=None, evlog=None):
+    st = init_state(scorer, topo, lig_id, prm, traj, evlog=evlog)
+    return run_steps(scorer, topo, lig_id, prm, st, prm.n_steps, traj, trace, evlog=evlog)

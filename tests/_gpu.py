@@ -72,6 +72,13 @@ def compare_eval(E, g, ref, n_dof, tag=""):
     ok_margin = ref["margin"] > MARGIN
     ok_e = ref["margin_E"] > MARGIN
     bad = (ok_e & (e_ratio > 1)) | (ok_margin & (g_ratio > 1))
+    # poses within the bound only thanks to the absolute floor (reported)
+    dg = np.linalg.norm(g[:, :n_dof] - gr, axis=1)
+    floor_only = ok_margin & (dg > G_RTOL * gn) & (g_ratio <= 1)
+    if np.any(floor_only):
+        say("%s: %d of %d poses within the gradient bound only by its 1e-4 floor (|g| %s, |dg| %s)"
+            % (tag, int(floor_only.sum()), int(ok_margin.sum()), np.array2string(gn[floor_only][:4], precision=3),
+               np.array2string(dg[floor_only][:4], precision=3)))
     if np.any(bad):
         i = int(np.flatnonzero(bad)[0])
         raise AssertionError(
