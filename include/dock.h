@@ -369,6 +369,22 @@ int dock_pocket_map_adjoint(dock_pocket_t p, const float* dLdG, float* dLdxyz, d
 int dock_screen_rank(const float* scores, int64_t n, int32_t stride, int32_t top_k, float* score_out,
                      int32_t* lig_out, void* stream);
 
+/* dock_screen_rank without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, ordering and outputs.
+ * The intermediate passes run in a static device array of
+ * 4 * DOCK_NOALLOC_RANK_ENTRIES * 4 bytes (4 MiB) that each GPU the library
+ * runs on holds until the process ends; the call needs
+ * ceil(n / 2048) * top_k <= DOCK_NOALLOC_RANK_ENTRIES when n > 2048 and
+ * returns DOCK_E_LIMIT otherwise (e.g. top_k = 1024 allows n up to 524,288,
+ * top_k = 16 up to 2^31 - 2).  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (other streams, other threads) race and
+ * give wrong results; calls ordered on one stream are safe.  The first call
+ * on a device looks up the array's address there (no allocation). */
+#define DOCK_NOALLOC_RANK_ENTRIES 262144
+int dock_screen_rank_noalloc(const float* scores, int64_t n, int32_t stride, int32_t top_k,
+                             float* score_out, int32_t* lig_out, void* stream);
+
 /* Raw Philox4x32-10 blocks from the sampler's generator (Salmon et al.,
  * SC'11): out[4i..4i+3] = Philox(counter = counters[4i..4i+3], key = (k0, k1)).
  * counters, out: device [n * 4] uint32.  For checking the random stream. */

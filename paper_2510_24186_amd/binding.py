@@ -99,6 +99,7 @@ _sig("dock_run_kernel_ms", C.c_int, _p, C.POINTER(_f32))
 _sig("dock_free_run", C.c_int, _p)
 _sig("dock_philox", C.c_int, _p, C.c_uint32, C.c_uint32, C.c_int64, _p, _p)
 _sig("dock_screen_rank", C.c_int, _p, C.c_int64, _i32, _i32, _p, _p, _p)
+_sig("dock_screen_rank_noalloc", C.c_int, _p, C.c_int64, _i32, _i32, _p, _p, _p)
 _sig("dock_pocket_map_adjoint", C.c_int, _p, _p, _p, _p, _p)
 _sig("dock_ligands_set_mdn", C.c_int, _p, _i32, _i32, _p)
 _sig("dock_best_poses", C.c_int, _p, _i32, _p, _p, _i32, _i32, _f32, _f32, _p, _p, _p, _p, _p, _i32,
@@ -543,6 +544,24 @@ def dock_screen_rank(scores, top_k, stride=1, stream=None):
     _check(lib.dock_screen_rank(_dptr(s), n, int(stride), int(top_k), _dptr(out_s), _dptr(out_i),
                                 _stream(stream)))
     return out_s, out_i
+
+
+def dock_screen_rank_noalloc(scores, top_k, score_out, lig_out, stride=1, n=None, stream=None):
+    """dock_screen_rank into caller-allocated outputs (float32 / int32 CUDA
+    tensors of at least top_k entries) with the library's static scratch:
+    the call itself allocates nothing.  n defaults to the number of scores
+    in `scores` at `stride`."""
+    import torch
+    s = _cuda_check(scores, torch.float32, "scores")
+    _cuda_check(score_out, torch.float32, "score_out")
+    _cuda_check(lig_out, torch.int32, "lig_out")
+    if score_out.numel() < top_k or lig_out.numel() < top_k:
+        raise ValueError("outputs hold fewer than top_k entries")
+    if n is None:
+        n = (s.numel() + stride - 1) // stride
+    _check(lib.dock_screen_rank_noalloc(_dptr(s), int(n), int(stride), int(top_k), _dptr(score_out),
+                                        _dptr(lig_out), _stream(stream)))
+    return score_out, lig_out
 
 
 def dock_pocket_map_adjoint(pocket, dLdG, dLdxyz=None, dLdtheta=None, stream=None):

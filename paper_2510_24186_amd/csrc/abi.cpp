@@ -1695,21 +1695,53 @@ int dock_pocket_map_adjoint(dock_pocket_t p, const float* dLdG, float* dLdxyz, d
   return DOCK_OK;
 }
 
-int dock_screen_rank(const float* scores, int64_t n, int32_t stride, int32_t top_k, float* score_out,
-                     int32_t* lig_out, void* stream) {
-  if (n < 0 || n > (int64_t(1) << 31) - 2) return fail(DOCK_E_ARG, "n must be in [0, 2^31 - 2]");
-  if (stride < 1) return fail(DOCK_E_ARG, "stride must be >= 1");
-  if (top_k < 1 || top_k > 1024) return fail(DOCK_E_ARG, "top_k must be in [1, 1024]");
-  if (!score_out || !lig_out || (n > 0 && !scores)) return fail(DOCK_E_ARG, "null array");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  // each pass keeps top_k of every block of kRankBlock entries (at least
-  // halving the count) until one block remains; its output is the answer
+// The rank passes of dock_screen_rank: each keeps top_k of every block of
+// kRankBlock entries (at least halving the count) until one block remains,
+// whose output is the answer.  bufs / ibufs: two ping-pong buffers of
+// ceil(n / kRankBlock) * top_k entries each (unused when one block holds n).
+static hipError_t rank_passes(const float* scores, int64_t n, int32_t stride, int32_t top_k, float* score_out,
+                              int32_t* lig_out, float* const bufs[2], int* const ibufs[2], hipStream_t s) {
   RankArgs a{};
   a.score = scores;
   a.idx = nullptr;
   a.n = n;
   a.stride = stride;
   a.k = top_k;
+  int cur = 0;
+  for (;;) {
+    const long long blocks = (a.n + kRankBlock - 1) / kRankBlock;
+    if (blocks <= 1) {
+      // final pass, straight into the outputs (n = 0: one block of empty slots)
+      a.out_score = score_out;
+      a.out_idx = lig_out;
+      return launch_rank(a, s);
+    }
+    a.out_score = bufs[cur];
+    a.out_idx = ibufs[cur];
+    const hipError_t e = launch_rank(a, s);
+    if (e != hipSuccess) return e;
+    a.score = bufs[cur];
+    a.idx = ibufs[cur];
+    a.n = blocks * top_k;
+    a.stride = 1;
+    cur ^= 1;
+  }
+}
+
+static int check_rank_args(const float* scores, int64_t n, int32_t stride, int32_t top_k, const float* score_out,
+                           const int32_t* lig_out) {
+  if (n < 0 || n > (int64_t(1) << 31) - 2) return fail(DOCK_E_ARG, "n must be in [0, 2^31 - 2]");
+  if (stride < 1) return fail(DOCK_E_ARG, "stride must be >= 1");
+  if (top_k < 1 || top_k > 1024) return fail(DOCK_E_ARG, "top_k must be in [1, 1024]");
+  if (!score_out || !lig_out || (n > 0 && !scores)) return fail(DOCK_E_ARG, "null array");
+  return DOCK_OK;
+}
+
+int dock_screen_rank(const float* scores, int64_t n, int32_t stride, int32_t top_k, float* score_out,
+                     int32_t* lig_out, void* stream) {
+  int rc = check_rank_args(scores, n, stride, top_k, score_out, lig_out);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const long long blocks0 = (n + kRankBlock - 1) / kRankBlock;
   float* bufs[2] = {nullptr, nullptr};
   int* ibufs[2] = {nullptr, nullptr};
@@ -1721,29 +1753,61 @@ int dock_screen_rank(const float* scores, int64_t n, int32_t stride, int32_t top
       if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&ibufs[b]), cap * sizeof(int), s);
     }
   }
-  int cur = 0;
-  while (e == hipSuccess) {
-    const long long blocks = (a.n + kRankBlock - 1) / kRankBlock;
-    if (blocks <= 1) {
-      // final pass, straight into the outputs (n = 0: one block of empty slots)
-      a.out_score = score_out;
-      a.out_idx = lig_out;
-      e = launch_rank(a, s);
-      break;
-    }
-    a.out_score = bufs[cur];
-    a.out_idx = ibufs[cur];
-    e = launch_rank(a, s);
-    a.score = bufs[cur];
-    a.idx = ibufs[cur];
-    a.n = blocks * top_k;
-    a.stride = 1;
-    cur ^= 1;
-  }
+  if (e == hipSuccess) e = rank_passes(scores, n, stride, top_k, score_out, lig_out, bufs, ibufs, s);
   for (int b = 0; b < 2; ++b) {
     if (bufs[b]) (void)hipFreeAsync(bufs[b], s);
     if (ibufs[b]) (void)hipFreeAsync(ibufs[b], s);
   }
+  if (e != hipSuccess) return fail(DOCK_E_HIP, hipGetErrorString(e));
+  return DOCK_OK;
+}
+
+// Scratch of dock_screen_rank_noalloc: the two ping-pong buffer pairs
+// (float scores, int ligand indices) of kNoAllocRankEntries entries each,
+// one copy per GPU for the life of the process.  Host code never passes this
+// name to a kernel: it stands for a host-side shadow, not the device address.
+// The address on each device comes from hipGetSymbolAddress (noalloc_scratch).
+constexpr size_t kNoAllocRankEntries = size_t(DOCK_NOALLOC_RANK_ENTRIES);
+static __device__ __align__(256) unsigned char scratch[4 * kNoAllocRankEntries * 4];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+static int noalloc_scratch(unsigned char** out) {
+  static std::mutex mu;
+  static std::map<int, unsigned char*> addr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(DOCK_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DOCK_E_HIP, std::string("scratch symbol address: ") + hipGetErrorString(e));
+    it = addr.emplace(dev, static_cast<unsigned char*>(p)).first;
+  }
+  *out = it->second;
+  return DOCK_OK;
+}
+
+int dock_screen_rank_noalloc(const float* scores, int64_t n, int32_t stride, int32_t top_k, float* score_out,
+                             int32_t* lig_out, void* stream) {
+  int rc = check_rank_args(scores, n, stride, top_k, score_out, lig_out);
+  if (rc) return rc;
+  const long long blocks0 = (n + kRankBlock - 1) / kRankBlock;
+  if (blocks0 > 1 && size_t(blocks0) * size_t(top_k) > kNoAllocRankEntries)
+    return fail(DOCK_E_LIMIT, "ceil(n / 2048) * top_k exceeds the static scratch (" +
+                                  std::to_string(kNoAllocRankEntries) + " entries)");
+  unsigned char* base = nullptr;
+  rc = noalloc_scratch(&base);
+  if (rc) return rc;
+  // every pass writes each entry it later reads: nothing needs clearing
+  float* bufs[2] = {reinterpret_cast<float*>(base), reinterpret_cast<float*>(base + 4 * kNoAllocRankEntries)};
+  int* ibufs[2] = {reinterpret_cast<int*>(base + 8 * kNoAllocRankEntries),
+                   reinterpret_cast<int*>(base + 12 * kNoAllocRankEntries)};
+  const hipError_t e = rank_passes(scores, n, stride, top_k, score_out, lig_out, bufs, ibufs,
+                                   reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(DOCK_E_HIP, hipGetErrorString(e));
   return DOCK_OK;
 }

@@ -118,3 +118,18 @@ def test_residue_and_mixture_argument_errors():
                                                 residue=np.array(residue, np.int32), stream=0)) == -1
     H = _one([0, 0], [3, 3], xyz[:2], [(0, 1)], [0])
     assert _code(lambda: D.dock_ligands_set_mdn(H, np.ones((2, 3, 2, 3), np.float32))) == -1
+
+
+def test_noalloc_rank_refuses_sizes_beyond_its_scratch():
+    # checked on the host before any device work: ceil(n / 2048) * top_k
+    # above the static scratch, bad top_k, null outputs
+    cap = 262144
+    fake = 4096  # a non-null address that the refused calls never touch
+    f = D.lib.dock_screen_rank_noalloc
+    n = 2048 * (cap // 1024) + 1  # 257 blocks x 1024 kept
+    assert f(fake, n, 1, 1024, fake, fake, None) == -3
+    assert f(fake, n, 1, 1021, fake, fake, None) == -3  # 257 x 1021 > 262,144
+    assert f(fake, 10, 1, 0, fake, fake, None) == -1
+    assert f(fake, 10, 1, 1025, fake, fake, None) == -1
+    assert f(fake, 10, 1, 8, None, fake, None) == -1
+    assert f(fake, -1, 1, 8, fake, fake, None) == -1
