@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define DOCK_ABI_VERSION 1
+#define DOCK_ABI_VERSION 2
 #define DOCK_MAX_ATOMS 128
 #define DOCK_MAX_TORS 32
 #define DOCK_N_TYPES 8
@@ -118,12 +118,21 @@ typedef struct {
  * returns after enqueueing; the maps are ready when the stream reaches it. */
 int dock_load_pocket(const dock_pocket_desc* desc, void* stream, dock_pocket_t* out);
 
+/* Builds the maps of an existing grid-mode handle again, in place, on
+ * `stream` (same receptor, grid and weights; kernels only, no allocation):
+ * for a step that redoes the whole path, map build included.  Work that
+ * reads the maps on other streams must be ordered against it by the caller.
+ * Direct-mode handles have no maps: DOCK_OK, nothing enqueued. */
+int dock_pocket_rebuild(dock_pocket_t p, void* stream);
+
 /* Device pointer to the combined maps M [8][nz][ny][nx] (per_term = 0) or to
  * G [8][K][nz][ny][nx] (per_term = 1, only if kept).  Owned by the handle. */
 int dock_pocket_maps(dock_pocket_t p, int32_t per_term, float** dev_ptr, int64_t* n_floats);
 /* Copies the maps of dock_pocket_maps into `dst` (device, n_floats) on `stream`. */
 int dock_pocket_copy_maps(dock_pocket_t p, int32_t per_term, float* dst, void* stream);
 int dock_pocket_terms(dock_pocket_t p, int32_t* preset, int32_t* n_terms, float* weights /* host [K] */);
+/* Frees the handle and its maps.  Returns DOCK_E_ARG (and frees nothing)
+ * while a run created with this pocket is alive: free the run first. */
 int dock_free_pocket(dock_pocket_t p);
 
 /* ------------------------------------------------------------------------
@@ -177,6 +186,7 @@ int dock_ligand_topology(dock_ligands_t L, int32_t lig, uint8_t* type, int32_t* 
                          int32_t* pairs, int32_t* bfs);
 int dock_ligands_count(dock_ligands_t L, int32_t* n_ligands, int32_t* max_atoms,
                        int32_t* max_tors, int64_t* total_atoms);
+/* Returns DOCK_E_ARG (and frees nothing) while a run over L is alive. */
 int dock_free_ligands(dock_ligands_t L);
 
 /* ------------------------------------------------------------------------
@@ -201,8 +211,7 @@ int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligand
  *   E = sum_k w_k (sum_i trilerp(G[t_i][k], x_i) + sum_pairs phi_k(r_ij)) + E_out
  * dock_score_terms evaluates it with caller-supplied maps and weights;
  * dock_score_adjoint ACCUMULATES (+=) the gradients of L = sum_p dLdE[p] E_p
- *   dL/dG[t][k][node]  trilinear corner weights x w_k x dLdE (atomic scatter,
- *                      summation order not deterministic),
+ *   dL/dG[t][k][node]  trilinear corner weights x w_k x dLdE,
  *   dL/dw_k            dLdE x (per-term map sum + per-term pair sum),
  *   dL/dx              dLdE x dE/dx (caller atom order), and
  *   dL/dq              dLdE x dE/dq (DOF mode only),
@@ -215,6 +224,20 @@ int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligand
  *   dLdG   host array [n_pockets] of device pointers (entries nullable) or NULL
  *   dLdw   device [n_pockets * K] or NULL;  dLdq, dLdx device or NULL
  * All pockets of a call share one preset; n_pockets <= 16.
+ *   deterministic  0: dL/dG and dL/dw by float atomics (summation order, and
+ *                     so the last bits, vary from call to call);
+ *                  1: bitwise repeatable.  dL/dG is summed as 64-bit
+ *                     integers: every corner contribution is rounded once to
+ *                     a multiple of 2^(e - 62), where 2^e bounds any node's
+ *                     sum (n_poses x max_p |dLdE_p| N_p x max_k |w_k|, per
+ *                     pocket), so the sum is exact and order-free; then it is
+ *                     converted and added to dLdG.  dL/dw is reduced over the
+ *                     poses in a fixed order.  Scratch (8 bytes per dL/dG
+ *                     entry, 4 (K + 1) bytes per pose) is allocated and
+ *                     released on the stream.  Non-finite dLdE or w make
+ *                     that pocket's dL/dG NaN.
+ * Ligand-internal pair forces are summed as fixed point in either mode, so
+ * E, dL/dq and dL/dx never depend on timing.
  * ---------------------------------------------------------------------- */
 int dock_score_terms(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
                      int64_t n_poses, const int32_t* pose_lig, const float* q, int32_t q_stride,
@@ -224,7 +247,7 @@ int dock_score_adjoint(const dock_pocket_t* pockets, int32_t n_pockets, dock_lig
                        int64_t n_poses, const int32_t* pose_lig, const float* q, int32_t q_stride,
                        const float* xyz, int32_t xyz_stride, const float* const* G, const float* w,
                        const float* dLdE, float* const* dLdG, float* dLdw, float* dLdq, float* dLdx,
-                       void* stream);
+                       int32_t deterministic, void* stream);
 
 /* ------------------------------------------------------------------------
  * Sampling (Methods, "Conformation sampling"; Fig. 2).  Each trajectory
@@ -254,6 +277,10 @@ typedef struct {
                                two atoms per lane keep their width) */
   float rms_alpha;          /* RMSprop smoothing (0.99) */
   float weight_decay;       /* AdamW decoupled weight decay (0.01) */
+  int32_t trace_lig_stride; /* record_trace: log ligands l with l % stride == 0
+                               (0 or 1: every ligand) */
+  int32_t trace_traj;       /* record_trace: log trajectories t < trace_traj of those
+                               ligands (0: all) */
 } dock_sample_params;
 
 void dock_sample_params_default(dock_sample_params* p);
@@ -287,6 +314,12 @@ int dock_autotune_clear(void);
 
 /* Advances every trajectory by n_steps more MC steps (resume). */
 int dock_run_advance(dock_run_t r, int32_t n_steps, void* stream);
+/* Starts the run over with a new seed: every trajectory redraws its initial
+ * pose and takes the run's n_steps MC steps again, in the run's own buffers
+ * with its plan and launches, exactly as dock_sample with that seed would.
+ * Enqueues kernels only (no allocation, no host synchronisation, no memset):
+ * repeated docking of the same ligand set without per-call setup. */
+int dock_run_restart(dock_run_t r, uint32_t seed, void* stream);
 
 typedef struct {
   int32_t n_ligands, n_traj, q_stride, step;
@@ -295,9 +328,14 @@ typedef struct {
   float* q_best;      /* device [n_ligands * n_traj * q_stride] */
   float* E_best;      /* device [n_ligands * n_traj] */
   int32_t* n_evals;   /* device [n_ligands * n_traj], evaluations so far */
-  float* trace;       /* device, record_trace only: per trajectory
-                         [trace_cap][2 * q_stride + 1] rows (q, dE/dq, E) */
+  float* trace;       /* device, record_trace only: per logged trajectory
+                         [trace_cap][2 * q_stride + 1] rows (q, dE/dq, E);
+                         trajectory t of ligand l (l % trace_lig_stride == 0,
+                         t < trace_traj) is block (l / trace_lig_stride) *
+                         trace_traj + t */
   int32_t trace_cap;  /* rows per trajectory */
+  int32_t trace_lig_stride, trace_traj;  /* as applied (>= 1) */
+  int32_t n_trace;    /* logged trajectories */
 } dock_run_view;
 
 int dock_run_view_get(dock_run_t r, dock_run_view* v);

@@ -53,13 +53,15 @@ class SampleParams(C.Structure):
                 ("lr", _f32), ("beta1", _f32), ("beta2", _f32), ("eps", _f32), ("mc_beta", _f32),
                 ("seed", C.c_uint32), ("form", _i32), ("use_graph", _i32),
                 ("steps_per_launch", _i32), ("record_trace", _i32), ("lanes_per_pose", _i32),
-                ("rms_alpha", _f32), ("weight_decay", _f32)]
+                ("rms_alpha", _f32), ("weight_decay", _f32), ("trace_lig_stride", _i32),
+                ("trace_traj", _i32)]
 
 
 class RunView(C.Structure):
     _fields_ = [("n_ligands", _i32), ("n_traj", _i32), ("q_stride", _i32), ("step", _i32),
                 ("q_cur", _p), ("E_cur", _p), ("q_best", _p), ("E_best", _p), ("n_evals", _p),
-                ("trace", _p), ("trace_cap", _i32)]
+                ("trace", _p), ("trace_cap", _i32), ("trace_lig_stride", _i32), ("trace_traj", _i32),
+                ("n_trace", _i32)]
 
 
 def _sig(name, res, *args):
@@ -73,6 +75,7 @@ _sig("dock_last_error", C.c_char_p)
 _sig("dock_abi_version", C.c_int)
 _sig("dock_load_pocket", C.c_int, C.POINTER(PocketDesc), _p, C.POINTER(_p))
 _sig("dock_pocket_maps", C.c_int, _p, _i32, C.POINTER(_p), C.POINTER(C.c_int64))
+_sig("dock_pocket_rebuild", C.c_int, _p, _p)
 _sig("dock_pocket_copy_maps", C.c_int, _p, _i32, _p, _p)
 _sig("dock_pocket_terms", C.c_int, _p, C.POINTER(_i32), C.POINTER(_i32), _p)
 _sig("dock_free_pocket", C.c_int, _p)
@@ -85,10 +88,11 @@ _sig("dock_free_ligands", C.c_int, _p)
 _sig("dock_score_grad", C.c_int, _p, _i32, _p, C.c_int64, _p, _p, _i32, _p, _p, _p, _i32, _p)
 _sig("dock_score_terms", C.c_int, _p, _i32, _p, C.c_int64, _p, _p, _i32, _p, _i32, _p, _p, _p, _p)
 _sig("dock_score_adjoint", C.c_int, _p, _i32, _p, C.c_int64, _p, _p, _i32, _p, _i32, _p, _p, _p, _p, _p,
-     _p, _p, _p)
+     _p, _p, _i32, _p)
 _sig("dock_sample_params_default", None, C.POINTER(SampleParams))
 _sig("dock_sample", C.c_int, _p, _i32, _p, C.POINTER(SampleParams), _p, C.POINTER(_p))
 _sig("dock_run_advance", C.c_int, _p, _i32, _p)
+_sig("dock_run_restart", C.c_int, _p, C.c_uint32, _p)
 _sig("dock_autotune", C.c_int, _p, _i32, _p, C.POINTER(SampleParams), _i32, _p)
 _sig("dock_autotune_report", C.c_int, C.c_char_p, _i32, C.POINTER(_i32))
 _sig("dock_autotune_clear", C.c_int)
@@ -166,7 +170,7 @@ class Pocket:
 
     def free(self):
         if self.handle:
-            lib.dock_free_pocket(self.handle)
+            _check(lib.dock_free_pocket(self.handle))
             self.handle = None
 
     def __del__(self):
@@ -211,6 +215,11 @@ def dock_pocket_terms(pocket):
     return pr.value, nk.value, w[:nk.value].copy()
 
 
+def dock_pocket_rebuild(pocket, stream=None):
+    """Builds the pocket's maps again in place on the stream."""
+    _check(lib.dock_pocket_rebuild(pocket.handle, _stream(stream)))
+
+
 def dock_pocket_maps(pocket, per_term=False, stream=None):
     """A copy of the maps as a CUDA tensor [8, (K,) nz, ny, nx]."""
     import torch
@@ -238,7 +247,7 @@ class Ligands:
 
     def free(self):
         if self.handle:
-            lib.dock_free_ligands(self.handle)
+            _check(lib.dock_free_ligands(self.handle))
             self.handle = None
 
     def __del__(self):
@@ -367,8 +376,9 @@ def dock_score_terms(pockets, L, pose_lig, w, q=None, xyz=None, G=None, stream=N
 
 
 def dock_score_adjoint(pockets, L, pose_lig, w, dLdE, q=None, xyz=None, G=None, dLdG=None, dLdw=None,
-                       dLdq=None, dLdx=None, stream=None):
-    """Accumulates (+=) gradients of sum_p dLdE[p] E_p into the given buffers."""
+                       dLdq=None, dLdx=None, deterministic=False, stream=None):
+    """Accumulates (+=) gradients of sum_p dLdE[p] E_p into the given buffers
+    (deterministic: bitwise repeatable dL/dG and dL/dw)."""
     import torch
     pockets, arr, npk, pose_lig, q, xyz, G, w = _terms_common(pockets, L, pose_lig, q, xyz, G, w)
     dLdE = _cuda_check(dLdE, torch.float32, "dLdE")
@@ -377,15 +387,17 @@ def dock_score_adjoint(pockets, L, pose_lig, w, dLdE, q=None, xyz=None, G=None, 
     xs = 3 * L.max_atoms
     _check(lib.dock_score_adjoint(arr, npk, L.handle, n, _dptr(pose_lig), _dptr(q), qs, _dptr(xyz), xs,
                                   _ptr_array(G, npk), _dptr(w), _dptr(dLdE), _ptr_array(dLdG, npk),
-                                  _dptr(dLdw), _dptr(dLdq), _dptr(dLdx), _stream(stream)))
+                                  _dptr(dLdw), _dptr(dLdq), _dptr(dLdx), int(bool(deterministic)),
+                                  _stream(stream)))
 
 
 # ------------------------------------------------------------------ sampling
 
 class Run:
-    def __init__(self, handle, L, n_traj):
+    def __init__(self, handle, L, n_traj, pockets=()):
         self.handle = handle
-        self.L = L
+        self.L = L  # the run reads the ligand and pocket handles until it is freed
+        self.pockets = list(pockets)
         self.n_traj = n_traj
 
     def view(self):
@@ -420,7 +432,7 @@ def dock_sample(pockets, L, stream=None, **params):
     arr, npk = _pocket_array(pockets)
     h = _p()
     _check(lib.dock_sample(arr, npk, L.handle, C.byref(p), _stream(stream), C.byref(h)))
-    return Run(h, L, p.n_traj)
+    return Run(h, L, p.n_traj, [pockets] if isinstance(pockets, Pocket) else pockets)
 
 
 def dock_autotune(pockets, L, trial_steps=2, stream=None, **params):
@@ -449,6 +461,12 @@ def dock_run_advance(run, n_steps, stream=None):
     _check(lib.dock_run_advance(run.handle, int(n_steps), _stream(stream)))
 
 
+def dock_run_restart(run, seed, stream=None):
+    """Redraws the initial poses with `seed` and reruns the run's MC steps in
+    place (same results as a new dock_sample with that seed)."""
+    _check(lib.dock_run_restart(run.handle, int(seed) & 0xFFFFFFFF, _stream(stream)))
+
+
 def dock_run_state(run, trace=False, stream=None):
     """Copies of the run state as CUDA tensors."""
     import torch
@@ -465,7 +483,8 @@ def dock_run_state(run, trace=False, stream=None):
     if trace:
         if not v.trace_cap:
             raise ValueError("run was not created with record_trace")
-        tr = torch.empty((v.n_ligands, v.n_traj, v.trace_cap, 2 * v.q_stride + 1), device=dev)
+        # [logged ligand (l / trace_lig_stride), trajectory < trace_traj, row, column]
+        tr = torch.empty((v.n_trace // v.trace_traj, v.trace_traj, v.trace_cap, 2 * v.q_stride + 1), device=dev)
         out["trace"] = tr
     _check(lib.dock_run_copy_state(run.handle, _dptr(out["q_cur"]), _dptr(out["E_cur"]),
                                    _dptr(out["q_best"]), _dptr(out["E_best"]),

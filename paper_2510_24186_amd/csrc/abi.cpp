@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -54,6 +55,8 @@ static void dev_free(T*& p) {
 
 struct dock_pocket_s {
   PocketDev dev{};   // host copy of the device descriptor
+  std::atomic<int> n_runs{0};  // live runs reading this pocket's device tables
+  MapArgs build{};   // the map build's arguments (grid mode), for dock_pocket_rebuild
   int n_rec = 0;
   float4* d_rec = nullptr;
   float* d_M = nullptr;
@@ -81,6 +84,7 @@ static void free_pocket_device(dock_pocket_s* p) {
 }
 
 struct dock_ligands_s {
+  std::atomic<int> n_runs{0};  // live runs reading these device arrays
   std::vector<LigandHost> host;
   std::vector<LigDev> h_ligs;
   int n = 0, max_atoms = 0, max_tors = 0, max_pairs = 0, max_frags = 0;
@@ -369,11 +373,19 @@ int dock_load_pocket(const dock_pocket_desc* d, void* stream, dock_pocket_t* out
   type_pair_table(d->preset, a.tab);
   a.G = p->d_G;
   a.M = p->d_M;
+  p->build = a;
   e = launch_map_build(a, s);
   if (e != hipSuccess) return cleanup(DOCK_E_HIP, std::string("map build: ") + hipGetErrorString(e));
   pd.M = p->d_M;
   pd.G = p->d_G;
   *out = p;
+  return DOCK_OK;
+}
+
+int dock_pocket_rebuild(dock_pocket_t p, void* stream) {
+  if (!p) return fail(DOCK_E_ARG, "null pocket");
+  if (p->dev.inter_mode != DOCK_INTER_GRID) return DOCK_OK;  // direct mode: no maps
+  HIP_TRY(launch_map_build(p->build, reinterpret_cast<hipStream_t>(stream)));
   return DOCK_OK;
 }
 
@@ -414,6 +426,9 @@ int dock_pocket_terms(dock_pocket_t p, int32_t* preset, int32_t* n_terms, float*
 
 int dock_free_pocket(dock_pocket_t p) {
   if (!p) return DOCK_OK;
+  if (p->n_runs.load() > 0)
+    return fail(DOCK_E_ARG, "pocket is still used by " + std::to_string(p->n_runs.load()) +
+                                " live run(s): free the runs first");
   drop_tables_with(p);
   (void)hipDeviceSynchronize();
   free_pocket_device(p);
@@ -793,6 +808,9 @@ int dock_ligands_count(dock_ligands_t L, int32_t* n_ligands, int32_t* max_atoms,
 
 int dock_free_ligands(dock_ligands_t L) {
   if (!L) return DOCK_OK;
+  if (L->n_runs.load() > 0)
+    return fail(DOCK_E_ARG, "ligand handle is still used by " + std::to_string(L->n_runs.load()) +
+                                " live run(s): free the runs first");
   if (!L->host_only) (void)hipDeviceSynchronize();
   free_ligand_device(L);
   delete L;
@@ -873,7 +891,7 @@ static int terms_call(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
                       const int32_t* pose_lig, const float* q, int32_t q_stride, const float* xyz,
                       int32_t xyz_stride, const float* const* G, const float* w, float* E,
                       const float* dLdE, float* const* dLdG, float* dLdw, float* dLdq, float* dLdx,
-                      void* stream) {
+                      int deterministic, void* stream) {
   if (!L) return fail(DOCK_E_ARG, "null ligands");
   int rc = check_pockets(pockets, n_pockets, L);
   if (rc) return rc;
@@ -922,7 +940,63 @@ static int terms_call(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   a.dLdq = dLdq;
   a.dLdx = dLdx;
   a.max_pairs = L->max_alt_pairs;
-  HIP_TRY(launch_terms(a, lpp, apl, K, reinterpret_cast<hipStream_t>(stream)));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (!(dLdE && deterministic)) {
+    HIP_TRY(launch_terms(a, lpp, apl, K, s));
+    return DOCK_OK;
+  }
+  // Deterministic adjoint: dL/dG summed as 64-bit integers (fixed point at a
+  // per-pocket power-of-two scale from a bound on every node's sum), dL/dw as
+  // per-pose contributions reduced in a fixed order.  Scratch is allocated on
+  // the stream and released after the last kernel that reads it.
+  long long off[kMaxDiffPockets + 1] = {0};
+  for (int i = 0; i < n_pockets; ++i) {
+    const GridDev& gd = pockets[i]->dev.grid;
+    const long long n = a.dLdG[i] ? (long long)kTypes * K * gd.dims[0] * gd.dims[1] * gd.dims[2] : 0;
+    off[i + 1] = off[i] + n;
+  }
+  unsigned long long* acc = nullptr;
+  double* scale = nullptr;
+  float* w_pose = nullptr;
+  int* w_pocket = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&scale), sizeof(double) * kMaxDiffPockets, s);
+  if (e == hipSuccess && off[n_pockets] > 0)
+    e = hipMallocAsync(reinterpret_cast<void**>(&acc), sizeof(unsigned long long) * off[n_pockets], s);
+  if (e == hipSuccess && dLdw) {
+    e = hipMallocAsync(reinterpret_cast<void**>(&w_pose), sizeof(float) * size_t(n_poses) * K, s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&w_pocket), sizeof(int) * size_t(n_poses), s);
+  }
+  if (e == hipSuccess && acc) e = launch_zero_u64(acc, off[n_pockets], s);
+  if (e == hipSuccess) {
+    AdjBoundArgs b{};
+    b.ligs = L->d_ligs;
+    b.n_ligands = L->n;
+    b.n_pockets = n_pockets;
+    b.K = K;
+    b.n_poses = n_poses;
+    b.pose_lig = pose_lig;
+    b.dLdE = dLdE;
+    b.w = w;
+    b.scale = scale;
+    e = launch_adj_bound(b, s);
+  }
+  if (e == hipSuccess) {
+    for (int i = 0; i < n_pockets; ++i) a.acc[i] = a.dLdG[i] ? acc + off[i] : nullptr;
+    a.acc_scale = scale;
+    a.w_pose = w_pose;
+    a.w_pocket = w_pocket;
+    a.dLdw = dLdw;
+    e = launch_terms(a, lpp, apl, K, s);
+  }
+  for (int i = 0; i < n_pockets && e == hipSuccess; ++i)
+    if (a.dLdG[i]) e = launch_adj_finalize(acc + off[i], scale + i, off[i + 1] - off[i], a.dLdG[i], s);
+  if (e == hipSuccess && dLdw) e = launch_adj_wreduce(w_pose, w_pocket, n_poses, n_pockets, K, dLdw, s);
+  for (void* p : {static_cast<void*>(acc), static_cast<void*>(scale), static_cast<void*>(w_pose),
+                  static_cast<void*>(w_pocket)})
+    if (p) (void)hipFreeAsync(p, s);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? DOCK_E_OOM : DOCK_E_HIP,
+                std::string("deterministic adjoint: ") + hipGetErrorString(e));
   return DOCK_OK;
 }
 
@@ -931,16 +1005,18 @@ int dock_score_terms(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligan
                      int32_t xyz_stride, const float* const* G, const float* w, float* E, void* stream) {
   if (!E) return fail(DOCK_E_ARG, "null E");
   return terms_call(pockets, n_pockets, L, n_poses, pose_lig, q, q_stride, xyz, xyz_stride, G, w, E, nullptr,
-                    nullptr, nullptr, nullptr, nullptr, stream);
+                    nullptr, nullptr, nullptr, nullptr, 0, stream);
 }
 
 int dock_score_adjoint(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L, int64_t n_poses,
                        const int32_t* pose_lig, const float* q, int32_t q_stride, const float* xyz,
                        int32_t xyz_stride, const float* const* G, const float* w, const float* dLdE,
-                       float* const* dLdG, float* dLdw, float* dLdq, float* dLdx, void* stream) {
+                       float* const* dLdG, float* dLdw, float* dLdq, float* dLdx, int32_t deterministic,
+                       void* stream) {
   if (!dLdE) return fail(DOCK_E_ARG, "null dLdE");
+  if (deterministic != 0 && deterministic != 1) return fail(DOCK_E_ARG, "deterministic must be 0 or 1");
   return terms_call(pockets, n_pockets, L, n_poses, pose_lig, q, q_stride, xyz, xyz_stride, G, w, nullptr, dLdE,
-                    dLdG, dLdw, dLdq, dLdx, stream);
+                    dLdG, dLdw, dLdq, dLdx, deterministic, stream);
 }
 
 // ================================================================ sampling
@@ -977,11 +1053,13 @@ struct Bucket {
 
 struct dock_run_s {
   dock_ligands_t L = nullptr;
-  std::vector<dock_pocket_t> pockets;
+  std::vector<dock_pocket_t> pockets;  // distinct handles, each counted in its n_runs
+  bool holds_refs = false;
   const PocketDev* table = nullptr;
   int mode = kModeGrid;             // kernel mode (eval_mode)
   dock_sample_params p{};
   int n_lig = 0, T = 0, q_stride = 0, step = 0, trace_cap = 0;
+  int trace_stride = 1, trace_tt = 0, n_trace = 0;  // logged ligands / trajectories
   float *q_cur = nullptr, *E_cur = nullptr, *q_best = nullptr, *E_best = nullptr, *trace = nullptr;
   int* n_evals = nullptr;
   int* d_step = nullptr;
@@ -1080,6 +1158,10 @@ static hipError_t timed_launch(dock_run_s* r, const SampleArgs& a, int bucket, i
 }
 
 static void free_run(dock_run_s* r) {
+  if (r->holds_refs) {
+    for (dock_pocket_t p : r->pockets) p->n_runs.fetch_sub(1);
+    r->L->n_runs.fetch_sub(1);
+  }
   for (hipEvent_t e : r->event_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : r->join) (void)hipEventDestroy(e);
   if (r->fork) (void)hipEventDestroy(r->fork);
@@ -1123,6 +1205,8 @@ static SampleArgs base_args(const dock_run_s* r) {
   a.n_evals = r->n_evals;
   a.trace = r->trace;
   a.trace_cap = r->trace_cap;
+  a.trace_stride = r->trace_stride;
+  a.trace_traj = r->trace_tt;
   return a;
 }
 
@@ -1242,6 +1326,7 @@ static int check_params(const dock_sample_params* p) {
         std::isfinite(p->weight_decay)))
     return fail(DOCK_E_ARG, "non-finite sampler constant");
   if (p->steps_per_launch < 0) return fail(DOCK_E_ARG, "negative steps_per_launch");
+  if (p->trace_lig_stride < 0 || p->trace_traj < 0) return fail(DOCK_E_ARG, "negative trace selection");
   return DOCK_OK;
 }
 
@@ -1264,6 +1349,13 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   if (!r) return fail(DOCK_E_OOM, "host allocation");
   r->L = L;
   r->pockets.assign(pockets, pockets + n_pockets);
+  std::sort(r->pockets.begin(), r->pockets.end());
+  r->pockets.erase(std::unique(r->pockets.begin(), r->pockets.end()), r->pockets.end());
+  // the run reads the pockets' tables and the ligands' arrays until it is
+  // freed: dock_free_pocket / dock_free_ligands refuse while it lives
+  for (dock_pocket_t pk : r->pockets) pk->n_runs.fetch_add(1);
+  L->n_runs.fetch_add(1);
+  r->holds_refs = true;
   r->mode = eval_mode(pockets, n_pockets, L);
   r->p = *p;
   r->n_lig = L->n;
@@ -1400,7 +1492,10 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   if (e == hipSuccess && p->record_trace) {
     const int per_step = p->local_opt == DOCK_LOCAL_LINESEARCH ? 1 + 11 * p->n_local : p->n_local + 1;
     r->trace_cap = 1 + p->n_steps * per_step;
-    e = dev_alloc(&r->trace, nt * size_t(r->trace_cap) * (2 * r->q_stride + 1));
+    r->trace_stride = std::max(1, p->trace_lig_stride);
+    r->trace_tt = p->trace_traj > 0 ? std::min(p->trace_traj, r->T) : r->T;
+    r->n_trace = ((r->n_lig + r->trace_stride - 1) / r->trace_stride) * r->trace_tt;
+    e = dev_alloc(&r->trace, size_t(r->n_trace) * size_t(r->trace_cap) * (2 * r->q_stride + 1));
   }
   if (e != hipSuccess) return bail(DOCK_E_OOM, std::string("run allocation: ") + hipGetErrorString(e));
   // the kernels write the n_dof leading slots of every pose row; the padding
@@ -1416,7 +1511,8 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   if (e == hipSuccess) e = launch_fill_int(r->d_step, 1, 0, s);
   if (e == hipSuccess && r->trace) {
     // trace rows default to NaN
-    e = hipMemsetAsync(r->trace, 0xff, nt * size_t(r->trace_cap) * (2 * r->q_stride + 1) * sizeof(float), s);
+    e = hipMemsetAsync(r->trace, 0xff,
+                       size_t(r->n_trace) * size_t(r->trace_cap) * (2 * r->q_stride + 1) * sizeof(float), s);
   }
   if (e != hipSuccess) return bail(DOCK_E_HIP, std::string("init: ") + hipGetErrorString(e));
   rc = timed_phases(r, true, p->n_steps, s);
@@ -1542,6 +1638,23 @@ int dock_run_advance(dock_run_t r, int32_t n_steps, void* stream) {
   return timed_phases(r, false, n_steps, s);
 }
 
+int dock_run_restart(dock_run_t r, uint32_t seed, void* stream) {
+  if (!r) return fail(DOCK_E_ARG, "null run");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t nt = size_t(r->n_lig) * r->T;
+  // counters and the trace back to their initial values with fill kernels
+  // (the call only enqueues kernels: it allocates nothing and can be
+  // captured into a graph)
+  HIP_TRY(launch_fill_int(r->n_evals, int(nt), 0, s));
+  HIP_TRY(launch_fill_int(r->d_step, 1, 0, s));
+  if (r->trace)
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(r->trace),
+                            (long long)r->n_trace * r->trace_cap * (2 * r->q_stride + 1), 0xffffffffu, s));
+  r->p.seed = seed;
+  r->step = 0;
+  return timed_phases(r, true, r->p.n_steps, s);
+}
+
 int dock_run_view_get(dock_run_t r, dock_run_view* v) {
   if (!r || !v) return fail(DOCK_E_ARG, "null argument");
   v->n_ligands = r->n_lig;
@@ -1555,6 +1668,9 @@ int dock_run_view_get(dock_run_t r, dock_run_view* v) {
   v->n_evals = r->n_evals;
   v->trace = r->trace;
   v->trace_cap = r->trace_cap;
+  v->trace_lig_stride = r->trace_stride;
+  v->trace_traj = r->trace_tt;
+  v->n_trace = r->n_trace;
   return DOCK_OK;
 }
 
@@ -1571,7 +1687,7 @@ int dock_run_copy_state(dock_run_t r, float* q_cur, float* E_cur, float* q_best,
   if (n_evals) HIP_TRY(hipMemcpyAsync(n_evals, r->n_evals, nt * sizeof(int), D2D, s));
   if (trace) {
     if (!r->trace) return fail(DOCK_E_ARG, "run has no trace");
-    HIP_TRY(hipMemcpyAsync(trace, r->trace, nt * size_t(r->trace_cap) * (2 * r->q_stride + 1) * sizeof(float),
+    HIP_TRY(hipMemcpyAsync(trace, r->trace, size_t(r->n_trace) * size_t(r->trace_cap) * (2 * r->q_stride + 1) * sizeof(float),
                            D2D, s));
   }
   return DOCK_OK;

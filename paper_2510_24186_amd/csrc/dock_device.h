@@ -1217,14 +1217,22 @@ DK_INLINE EvalOut eval_pose(const LaneLig<APL>& Lin, float q, const PocketDev& p
 
 // Differentiable form: the score over per-term maps G[t][k] with weights w
 // (E = sum_k w_k (sum_i trilerp(G[t_i][k], x_i) + sum_pairs phi_k) + E_out),
-// optionally scattering dL/dG for dL/dE = dLdE.  Atom positions come from FK
-// of q (XIN = false) or are given (XIN = true).  Leaves per-atom gradients in
-// g, per-term sums (reduced over the group) in ek, and returns E.
+// optionally scattering dL/dG for dL/dE = dLdE: into the float maps dLdG by
+// float atomics, or (acc non-null) into 64-bit fixed-point accumulators, each
+// corner weight rounded once to an integer multiple of 1 / acc_scale (a power
+// of two; 0 marks a non-finite bound and drops the scatter).  Integer sums do
+// not depend on the order of the atomics.  Intra-pair forces are summed in
+// LDS as 64-bit fixed point scaled from a bound on the pair forces, which
+// makes them independent of the atomics' order as well.  Atom positions
+// come from FK of q (XIN = false) or are given (XIN = true).  Leaves
+// per-atom gradients in g, per-term sums (reduced over the group) in ek, and
+// returns E.
 template <int LPP, int APL, int K, bool XIN>
 DK_INLINE float eval_terms(const LaneLig<APL>& L, float q, float (&x)[APL][3], float (&g)[APL][3],
                            Rigid& rg, const float* __restrict__ G, const GridDev& grid,
                            const float (&w)[K], const PairRec* __restrict__ pairs, const GroupSlab& S,
-                           int r, float dLdE, float* __restrict__ dLdG, float (&ek)[K]) {
+                           int r, float dLdE, float* __restrict__ dLdG, float (&ek)[K],
+                           unsigned long long* __restrict__ acc = nullptr, double acc_scale = 0.0) {
   if (!XIN) rg = fk_place<LPP, APL>(L, q, r, x, S.xs);
   const size_t nxyz = size_t(grid.dims[0]) * grid.dims[1] * grid.dims[2];
   const int nx = grid.dims[0], nxy = grid.dims[0] * grid.dims[1];
@@ -1257,18 +1265,27 @@ DK_INLINE float eval_terms(const LaneLig<APL>& L, float q, float (&x)[APL][3], f
           g[s][1] += sy;
           g[s][2] += sz;
         }
-        if (dLdG) {
-          float* d = dLdG + size_t(L.atype[s] * K + k) * nxyz + tl.base;
+        if (dLdG || acc) {
+          const size_t off = size_t(L.atype[s] * K + k) * nxyz + tl.base;
           const float c = dLdE * w[k];
           const float fx = tl.fx, fy = tl.fy, fz = tl.fz;
-          atomicAdd(d, c * (1.f - fx) * (1.f - fy) * (1.f - fz));
-          atomicAdd(d + 1, c * fx * (1.f - fy) * (1.f - fz));
-          atomicAdd(d + nx, c * (1.f - fx) * fy * (1.f - fz));
-          atomicAdd(d + nx + 1, c * fx * fy * (1.f - fz));
-          atomicAdd(d + nxy, c * (1.f - fx) * (1.f - fy) * fz);
-          atomicAdd(d + nxy + 1, c * fx * (1.f - fy) * fz);
-          atomicAdd(d + nxy + nx, c * (1.f - fx) * fy * fz);
-          atomicAdd(d + nxy + nx + 1, c * fx * fy * fz);
+          const float cv[8] = {c * (1.f - fx) * (1.f - fy) * (1.f - fz), c * fx * (1.f - fy) * (1.f - fz),
+                               c * (1.f - fx) * fy * (1.f - fz),         c * fx * fy * (1.f - fz),
+                               c * (1.f - fx) * (1.f - fy) * fz,         c * fx * (1.f - fy) * fz,
+                               c * (1.f - fx) * fy * fz,                 c * fx * fy * fz};
+          const size_t co[8] = {0, 1, size_t(nx), size_t(nx) + 1, size_t(nxy), size_t(nxy) + 1,
+                                size_t(nxy) + nx, size_t(nxy) + nx + 1};
+          if (acc) {
+            if (acc_scale > 0.0) {
+#pragma unroll
+              for (int cn = 0; cn < 8; ++cn)
+                atomicAdd(acc + off + co[cn],
+                          static_cast<unsigned long long>(__double2ll_rn(double(cv[cn]) * acc_scale)));
+            }
+          } else {
+#pragma unroll
+            for (int cn = 0; cn < 8; ++cn) atomicAdd(dLdG + off + co[cn], cv[cn]);
+          }
         }
       }
       S.xs[atom] = make_float4(x[s][0], x[s][1], x[s][2], 0.f);
@@ -1278,6 +1295,30 @@ DK_INLINE float eval_terms(const LaneLig<APL>& L, float q, float (&x)[APL][3], f
     }
   }
   wave_sync();
+  // The force slots (zeroed above as 0.0, i.e. integer 0) hold fixed-point
+  // sums.  An atom takes at most 127 pair forces, each at most
+  // sum_k |w_k| D_k in magnitude, with D_k >= max |d phi_k / dd| over
+  // d >= 0.1 (below 0.1 the clash term is flat): TRIDS 1/sqrt(2e), 1/0.1,
+  // 2 * 0.3/0.18 * e^-1/2; Vina sqrt(8) e^-1/2, 1/sqrt(2e), 2 * 3.8, 1,
+  // 1/0.7, each rounded up.  The scale 2^(62 - e) with 127 sum_k |w_k| D_k
+  // <= 2^e keeps every sum inside the signed 64-bit range.
+  unsigned long long* fxi = reinterpret_cast<unsigned long long*>(S.fx);
+  unsigned long long* fyi = reinterpret_cast<unsigned long long*>(S.fy);
+  unsigned long long* fzi = reinterpret_cast<unsigned long long*>(S.fz);
+  double force_fix = 0.0, force_unfix = 0.0;
+  {
+    constexpr float kD3[3] = {0.5f, 10.0f, 2.1f};
+    constexpr float kD5[5] = {1.8f, 0.5f, 8.0f, 1.0f, 1.5f};
+    double fb = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) fb += fabs(double(w[k])) * double(K == 3 ? kD3[k % 3] : kD5[k % 5]);
+    if (fb < 1e300) {  // finite weights (else the intra forces drop out)
+      int ex = 0;
+      (void)frexp(127.0 * fb, &ex);
+      force_fix = ldexp(1.0, 62 - ex);
+      force_unfix = ldexp(1.0, ex - 62);
+    }
+  }
   const int pstep = L.n_pass > 0 ? 2 : 1;
   for (int p = r; p < L.n_prec; p += LPP) {
     const PairRec pr = pairs[pstep * p];
@@ -1297,12 +1338,15 @@ DK_INLINE float eval_terms(const LaneLig<APL>& L, float q, float (&x)[APL][3], f
     }
     if (de != 0.f && d > 0.f) {
       const float c = de / d;
-      atomicAdd(&S.fx[i], double(c * dx));
-      atomicAdd(&S.fy[i], double(c * dy));
-      atomicAdd(&S.fz[i], double(c * dz));
-      atomicAdd(&S.fx[j], -double(c * dx));
-      atomicAdd(&S.fy[j], -double(c * dy));
-      atomicAdd(&S.fz[j], -double(c * dz));
+      const long long ix = __double2ll_rn(double(c * dx) * force_fix),
+                      iy = __double2ll_rn(double(c * dy) * force_fix),
+                      iz = __double2ll_rn(double(c * dz) * force_fix);
+      atomicAdd(&fxi[i], static_cast<unsigned long long>(ix));
+      atomicAdd(&fyi[i], static_cast<unsigned long long>(iy));
+      atomicAdd(&fzi[i], static_cast<unsigned long long>(iz));
+      atomicAdd(&fxi[j], static_cast<unsigned long long>(-ix));
+      atomicAdd(&fyi[j], static_cast<unsigned long long>(-iy));
+      atomicAdd(&fzi[j], static_cast<unsigned long long>(-iz));
     }
   }
   wave_sync();
@@ -1310,9 +1354,9 @@ DK_INLINE float eval_terms(const LaneLig<APL>& L, float q, float (&x)[APL][3], f
   for (int s = 0; s < APL; ++s) {
     const int atom = APL * r + s;
     if (atom < L.n_atoms) {
-      g[s][0] += float(S.fx[atom]);
-      g[s][1] += float(S.fy[atom]);
-      g[s][2] += float(S.fz[atom]);
+      g[s][0] += float(double(static_cast<long long>(fxi[atom])) * force_unfix);
+      g[s][1] += float(double(static_cast<long long>(fyi[atom])) * force_unfix);
+      g[s][2] += float(double(static_cast<long long>(fzi[atom])) * force_unfix);
     }
   }
   float E = group_sum<LPP>(eout);

@@ -55,7 +55,35 @@ struct TermsArgs {
   float* dLdq;
   float* dLdx;
   int max_pairs;
+  // deterministic adjoint (null otherwise): dL/dG into 64-bit fixed-point
+  // accumulators acc[pocket] (layout of dLdG) at scale acc_scale[pocket];
+  // dL/dw as per-pose contributions w_pose [n_poses * K] and the pose's
+  // pocket w_pocket [n_poses] (-1: invalid ligand), reduced afterwards
+  unsigned long long* acc[kMaxDiffPockets];
+  const double* acc_scale;
+  float* w_pose;
+  int* w_pocket;
 };
+
+// Deterministic adjoint helpers.
+struct AdjBoundArgs {
+  const LigDev* ligs;
+  int n_ligands, n_pockets, K;
+  long long n_poses;
+  const int* pose_lig;
+  const float* dLdE;
+  const float* w;       // [n_pockets * K]
+  double* scale;        // out [n_pockets]: 2^(62 - e), 0 for a non-finite bound
+};
+hipError_t launch_adj_bound(const AdjBoundArgs& a, hipStream_t s);
+// dLdG[i] += acc[i] / scale (NaN where scale = 0), i < n
+hipError_t launch_adj_finalize(const unsigned long long* acc, const double* scale, long long n, float* dLdG,
+                               hipStream_t s);
+// dLdw[pi * K + k] += sum over poses p with w_pocket[p] == pi of w_pose[p * K + k],
+// in a fixed order
+hipError_t launch_adj_wreduce(const float* w_pose, const int* w_pocket, long long n_poses, int n_pockets, int K,
+                              float* dLdw, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, long long n, hipStream_t s);
 
 struct SampleArgs {
   LigandArrays L;
@@ -78,6 +106,7 @@ struct SampleArgs {
   int* n_evals;
   float* trace;
   int trace_cap;
+  int trace_stride, trace_traj;  // logged: ligands l % stride == 0, trajectories < trace_traj
   int max_pairs;
 };
 
@@ -151,6 +180,7 @@ hipError_t launch_terms(const TermsArgs& a, int lpp, int apl, int K, hipStream_t
 hipError_t launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, long long n, uint32_t* out,
                          hipStream_t s);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s);
 hipError_t launch_add_int(int* p, int v, hipStream_t s);
 int sample_max_blocks_per_cu(int lpp, int apl, int block, int mode, size_t lds);
 

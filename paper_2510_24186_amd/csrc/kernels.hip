@@ -14,6 +14,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "dock_device.h"
 #include "dock_kernels.h"
 
@@ -343,6 +345,7 @@ __global__ void __launch_bounds__(64) terms_kernel(TermsArgs a) {
   const int lig = a.pose_lig[pose];
   if (lig < 0 || lig >= a.n_ligands) {
     if (r == 0 && a.E) a.E[pose] = __int_as_float(0x7fc00000);
+    if (r == 0 && a.w_pocket) a.w_pocket[pose] = -1;
     return;
   }
   LigDev lg = a.L.ligs[lig];
@@ -372,11 +375,18 @@ __global__ void __launch_bounds__(64) terms_kernel(TermsArgs a) {
     q = r < lg.n_dof ? a.q[pose * a.q_stride + r] : 0.f;
   }
   const float dLdE = a.dLdE ? a.dLdE[pose] : 0.f;
+  const bool det = a.acc_scale != nullptr;
   const float E = eval_terms<LPP, APL, K, XIN>(L, q, x, g, rg, a.G[pi], pk.grid, w, gp, S, r, dLdE,
-                                               a.dLdE ? a.dLdG[pi] : nullptr, ek);
+                                               (a.dLdE && !det) ? a.dLdG[pi] : nullptr, ek,
+                                               (a.dLdE && det) ? a.acc[pi] : nullptr,
+                                               det ? a.acc_scale[pi] : 0.0);
   if (r == 0 && a.E) a.E[pose] = E;
   if (!a.dLdE) return;
-  if (r == 0 && a.dLdw) {
+  if (r == 0 && a.w_pose) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) a.w_pose[pose * K + k] = dLdE * ek[k];
+    a.w_pocket[pose] = pi;
+  } else if (r == 0 && a.dLdw) {
 #pragma unroll
     for (int k = 0; k < K; ++k) atomicAdd(&a.dLdw[pi * K + k], dLdE * ek[k]);
   }
@@ -424,6 +434,121 @@ hipError_t launch_terms(const TermsArgs& a, int lpp, int apl, int K, hipStream_t
              : launch_terms_k<5, false>(a, lpp, apl, blocks, lds, s);
 }
 
+// ================================================================ deterministic adjoint
+
+// One workgroup: per pocket, the bound B = n_poses * max_p(|dLdE_p| N_p) *
+// max_k |w_k| on any node's |dL/dG| (each atom's eight corner weights are
+// non-negative and sum to one), and the fixed-point scale 2^(62 - e) with
+// B <= 2^e.  Maxima do not depend on the order of evaluation.
+__global__ void __launch_bounds__(256) adj_bound_kernel(AdjBoundArgs a) {
+  __shared__ float red[kMaxDiffPockets][256];
+  float m[kMaxDiffPockets];
+#pragma unroll
+  for (int k = 0; k < kMaxDiffPockets; ++k) m[k] = 0.f;
+  for (long long p = threadIdx.x; p < a.n_poses; p += 256) {
+    const int lig = a.pose_lig[p];
+    if (lig < 0 || lig >= a.n_ligands) continue;
+    const LigDev& lg = a.ligs[lig];
+    float v = fabsf(a.dLdE[p]) * float(lg.n_atoms);
+    if (!(v <= FLT_MAX)) v = INFINITY;  // NaN counts as unbounded
+#pragma unroll
+    for (int k = 0; k < kMaxDiffPockets; ++k)
+      if (k == lg.pocket) m[k] = fmaxf(m[k], v);
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxDiffPockets; ++k) red[k][threadIdx.x] = m[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int k = 0; k < kMaxDiffPockets; ++k) red[k][threadIdx.x] = fmaxf(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+    __syncthreads();
+  }
+  const int pi = threadIdx.x;
+  if (pi < a.n_pockets) {
+    float mw = 0.f;
+    for (int k = 0; k < a.K; ++k) {
+      float v = fabsf(a.w[pi * a.K + k]);
+      if (!(v <= FLT_MAX)) v = INFINITY;
+      mw = fmaxf(mw, v);
+    }
+    const double B = double(a.n_poses) * double(red[pi][0]) * double(mw);
+    double scale = 1.0;
+    if (!(B <= DBL_MAX)) {
+      scale = 0.0;
+    } else if (B > 0.0) {
+      int ex = 0;
+      (void)frexp(B, &ex);
+      scale = ldexp(1.0, 62 - ex);
+    }
+    a.scale[pi] = scale;
+  }
+}
+
+hipError_t launch_adj_bound(const AdjBoundArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(adj_bound_kernel, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void adj_finalize_kernel(const unsigned long long* __restrict__ acc, const double* scale, long long n,
+                                    float* __restrict__ dLdG) {
+  const double sc = *scale;
+  const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float v = sc > 0.0 ? float(double(static_cast<long long>(acc[i])) * inv) : __int_as_float(0x7fc00000);
+    dLdG[i] += v;
+  }
+}
+
+hipError_t launch_adj_finalize(const unsigned long long* acc, const double* scale, long long n, float* dLdG,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(adj_finalize_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, acc, scale, n, dLdG);
+  return hipGetLastError();
+}
+
+// One workgroup per (pocket, term): thread t sums poses t, t + 256, ... in
+// order, then a fixed tree over the workgroup.
+__global__ void __launch_bounds__(256) adj_wreduce_kernel(const float* __restrict__ w_pose,
+                                                          const int* __restrict__ w_pocket, long long n_poses,
+                                                          int K, float* dLdw) {
+  __shared__ float red[256];
+  const int pi = blockIdx.x / K, k = blockIdx.x % K;
+  float acc = 0.f;
+  for (long long p = threadIdx.x; p < n_poses; p += 256)
+    if (w_pocket[p] == pi) acc += w_pose[p * K + k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dLdw[pi * K + k] += red[0];
+}
+
+hipError_t launch_adj_wreduce(const float* w_pose, const int* w_pocket, long long n_poses, int n_pockets, int K,
+                              float* dLdw, hipStream_t s) {
+  if (n_pockets * K <= 0) return hipSuccess;
+  hipLaunchKernelGGL(adj_wreduce_kernel, dim3(unsigned(n_pockets * K)), dim3(256), 0, s, w_pose, w_pocket,
+                     n_poses, K, dLdw);
+  return hipGetLastError();
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
 // ================================================================ sampler
 
 template <int APL>
@@ -441,7 +566,9 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const Pocket
   const bool dof = r < L.n_dof;
   const int qs = a.q_stride;
   int nev = a.n_evals[ti];
-  float* trow = a.trace ? a.trace + ti * size_t(a.trace_cap) * (2 * qs + 1) : nullptr;
+  float* trow = nullptr;
+  if (a.trace && lig % a.trace_stride == 0 && traj < a.trace_traj)
+    trow = a.trace + (size_t(lig / a.trace_stride) * a.trace_traj + traj) * size_t(a.trace_cap) * (2 * qs + 1);
   auto record = [&](float qv, float gv, float Ev) {
     if (trow && nev < a.trace_cap) {
       float* row = trow + size_t(nev) * (2 * qs + 1);
@@ -867,6 +994,17 @@ __global__ void add_int_kernel(int* p, int v) {
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+__global__ void fill_u32_kernel(uint32_t* p, long long n, uint32_t v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+hipError_t launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 hipError_t launch_add_int(int* p, int v, hipStream_t s) {

@@ -208,16 +208,68 @@ def pack_ligands(parts):
                    rotatable=cat("rotatable", np.uint8, (0,)))
 
 
-def make_ligands(n_ligands, n_atoms, n_tors, seed=0, center_jitter=1.0, stream=2):
-    """`n_atoms` / `n_tors`: ints, or callables rng -> int drawn per ligand."""
-    parts = []
-    for i in range(n_ligands):
-        rng = _rng(seed, stream, i)
-        na = n_atoms(rng) if callable(n_atoms) else int(n_atoms)
-        nt = n_tors(rng) if callable(n_tors) else int(n_tors)
-        c = rng.normal(size=3) * center_jitter
-        parts.append(make_ligand(na, nt, rng, center=c))
+def _draw_ligand(i, n_atoms, n_tors, seed, center_jitter, stream):
+    rng = _rng(seed, stream, i)
+    na = n_atoms(rng) if callable(n_atoms) else int(n_atoms)
+    nt = n_tors(rng) if callable(n_tors) else int(n_tors)
+    c = rng.normal(size=3) * center_jitter
+    return make_ligand(na, nt, rng, center=c)
+
+
+def _draw_chunk(args):
+    lo, hi, n_atoms, n_tors, seed, center_jitter, stream = args
+    return [_draw_ligand(i, n_atoms, n_tors, seed, center_jitter, stream) for i in range(lo, hi)]
+
+
+def make_ligands(n_ligands, n_atoms, n_tors, seed=0, center_jitter=1.0, stream=2, workers=1):
+    """`n_atoms` / `n_tors`: ints, or callables rng -> int drawn per ligand.
+
+    Ligand i is drawn from its own seeded generator, so the result does not
+    depend on `workers` (> 1: processes of a spawn pool; the callables must
+    then be module-level functions)."""
+    if workers > 1 and n_ligands >= 256:
+        import multiprocessing as mp
+        step = (n_ligands + 4 * workers - 1) // (4 * workers)
+        jobs = [(lo, min(n_ligands, lo + step), n_atoms, n_tors, seed, center_jitter, stream)
+                for lo in range(0, n_ligands, step)]
+        with mp.get_context("spawn").Pool(workers) as pool:
+            parts = [p for chunk in pool.map(_draw_chunk, jobs) for p in chunk]
+    else:
+        parts = [_draw_ligand(i, n_atoms, n_tors, seed, center_jitter, stream) for i in range(n_ligands)]
     return pack_ligands(parts)
+
+
+# per-ligand size distributions of the workloads (module-level so that pool
+# workers can receive them)
+def _atoms_10_60(r):
+    return int(r.integers(10, 61))
+
+
+def _tors_0_15(r):
+    return int(r.integers(0, 16))
+
+
+def _atoms_c4(r):
+    # skewed toward 25-35 heavy atoms within 15-50
+    return int(np.clip(np.rint(r.normal(30.0, 5.0)), 15, 50))
+
+
+def _tors_0_12(r):
+    return int(r.integers(0, 13))
+
+
+def _atoms_10_70(r):
+    return int(r.integers(10, 71))
+
+
+def default_workers():
+    """Processes for drawing large ligand sets: the host's cores, at most 16."""
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 # ---------------------------------------------------------------------------
@@ -238,43 +290,54 @@ WORKLOADS = {
 }
 
 
-def workload(name, seed=0, n_lig=None):
+def workload(name, seed=0, n_lig=None, workers=1, ligand_ids=None):
     """(pockets, ligands, sampling dict) for one of the five workloads.
 
     `n_lig` truncates the ligand list (the first n ligands of the full
-    workload, identical to the full draw's first n).
+    workload, identical to the full draw's first n); `ligand_ids` instead
+    draws just the listed ligands of the full workload (pocket_index kept).
+    `workers` > 1 draws the ligands in a process pool (same result).
     """
     w = WORKLOADS[name]
     nl = w["n_lig"] if n_lig is None else int(n_lig)
+
+    def ligands(n_atoms, n_tors, stream):
+        if ligand_ids is None:
+            return make_ligands(nl, n_atoms, n_tors, seed=seed, stream=stream, workers=workers)
+        return pack_ligands([_draw_ligand(int(i), n_atoms, n_tors, seed, 1.0, stream) for i in ligand_ids])
+
     if name == "C1":
         pockets = [make_pocket(600, radius=15.0, grid=40, seed=seed)]
-        ligs = make_ligands(nl, 24, 4, seed=seed)
+        ligs = ligands(24, 4, 2)
     elif name in ("C2", "C3"):
         pockets = [make_pocket(2000, grid=64, seed=seed)]
         sub = 0 if name == "C2" else 1
-        ligs = make_ligands(nl, lambda r: int(r.integers(10, 61)),
-                            lambda r: int(r.integers(0, 16)), seed=seed,
-                            stream=2 + sub)
+        ligs = ligands(_atoms_10_60, _tors_0_15, 2 + sub)
     elif name == "C4":
         pockets = [make_pocket(2000, grid=64, seed=seed)]
-        ligs = make_ligands(
-            nl, lambda r: int(np.clip(np.rint(r.normal(30.0, 5.0)), 15, 50)),
-            lambda r: int(r.integers(0, 13)), seed=seed, stream=4)
+        ligs = ligands(_atoms_c4, _tors_0_12, 4)
     elif name == "C5":
-        rng = _rng(seed, 5)
-        pockets = []
-        for p in range(16):
-            n_rec = int(rng.integers(800, 3001))
-            side = int(rng.choice(np.arange(48, 97, 8)))
-            pockets.append(make_pocket(n_rec, grid=side, seed=seed * 100 + p + 1))
-        ligs = make_ligands(nl, lambda r: int(r.integers(10, 71)),
-                            lambda r: int(r.integers(0, 16)), seed=seed, stream=5)
-        ligs.pocket_index = (np.arange(nl) % 16).astype(np.int32)
+        pockets = c5_pockets(seed)
+        ligs = ligands(_atoms_10_70, _tors_0_15, 5)
+        ids = np.arange(nl) if ligand_ids is None else np.asarray(ligand_ids)
+        ligs.pocket_index = (ids % 16).astype(np.int32)
     else:
         raise KeyError(name)
     if ligs.pocket_index is None:
         ligs.pocket_index = np.zeros(nl, np.int32)
     return pockets, ligs, dict(T=w["T"], S=w["S"])
+
+
+def c5_pockets(seed=0):
+    """The 16 pockets of the mixed-pocket workload: 800-3,000 atoms, grid
+    sides 48-96 nodes in steps of 8, at the same atom density."""
+    rng = _rng(seed, 5)
+    pockets = []
+    for p in range(16):
+        n_rec = int(rng.integers(800, 3001))
+        side = int(rng.choice(np.arange(48, 97, 8)))
+        pockets.append(make_pocket(n_rec, grid=side, seed=seed * 100 + p + 1))
+    return pockets
 
 
 def random_poses(n_dof, box_min, box_max, n, rng):

@@ -301,3 +301,30 @@ def check_linesearch_log(rows, n_rows, n_dof, n_local, box_min, box_max):
             if not acc:
                 break
     return n_trials, n_acc, n_band
+
+
+class _Log:
+    def __init__(self, rows):
+        self.rows = rows
+
+
+def oracle_run(args):
+    """Pool worker: the oracle's own run of the listed trajectories of one
+    ligand (a lazily filled grid scorer on its pocket) with its evaluation
+    log.  args = (pocket, preset, weights, ligands, index in `ligands`,
+    ligand id (the Philox key), SamplerParams fields, trajectories).
+    Returns (rows per trajectory, per-step Metropolis margins)."""
+    pocket, preset, weights, ligs, i, lig_id, prm_kw, traj = args
+    from oracle import topology, score as SC, sampler as SM
+    topo = topology.from_ligands(ligs, i)
+    sc = SC.LazyScorer(pocket, preset, weights=np.asarray(weights, np.float64))
+    evlog, mct = SM.EvalLog(len(traj)), []
+    SM.sample(sc, topo, int(lig_id), SM.SamplerParams(**prm_kw), traj=np.asarray(traj), trace=mct, evlog=evlog)
+    return evlog.rows, [t["margin"] for t in mct]
+
+
+def compare_prefix(gpu_trace, gpu_nev, rows, margins, kind, n_local, lr, n_dof):
+    """compare_run over the oracle's (shorter) run: each GPU log is cut to
+    the oracle's row count when it holds at least as many rows."""
+    nev = np.asarray([min(int(g), len(r)) for g, r in zip(gpu_nev, rows)])
+    return compare_run(gpu_trace, nev, _Log(rows), [dict(margin=m) for m in margins], kind, n_local, lr, n_dof)

@@ -59,10 +59,11 @@ def _lazy_terms(pk, preset, grid, xs):
     return Gd
 
 
+@pytest.mark.parametrize("det", [0, 1])
 @pytest.mark.parametrize("preset", [P.PRESET_TRIDS, P.PRESET_VINA])
 @pytest.mark.parametrize("mode", ["q", "xyz"])
-def test_adjoint_tiny_against_oracle(D, preset, mode):
-    G.say("adjoint tiny preset", preset, "mode", mode)
+def test_adjoint_tiny_against_oracle(D, preset, mode, det):
+    G.say("adjoint tiny preset", preset, "mode", mode, "deterministic", det)
     pk = tiny_pocket(n=30, radius=7.0, grid=32)
     grid = SC.grid_of(pk)
     K = P.n_terms(preset)
@@ -90,8 +91,17 @@ def test_adjoint_tiny_against_oracle(D, preset, mode):
     dLdq = torch.zeros((len(Q), H.q_stride), device="cuda") if mode == "q" else None
     dLdx = torch.zeros((len(Q), H.max_atoms, 3), device="cuda")
     D.dock_score_adjoint(p, H, lt, wt, torch.tensor(dLdE, device="cuda"), G=[Ggpu], dLdG=[dLdG], dLdw=dLdw,
-                         dLdq=dLdq, dLdx=dLdx, **kw)
+                         dLdq=dLdq, dLdx=dLdx, deterministic=det, **kw)
     torch.cuda.synchronize()
+    if det:
+        # a second deterministic call repeats every output bit for bit
+        again = [torch.zeros_like(t) if t is not None else None for t in (dLdG, dLdw, dLdq, dLdx)]
+        D.dock_score_adjoint(p, H, lt, wt, torch.tensor(dLdE, device="cuda"), G=[Ggpu], dLdG=[again[0]],
+                             dLdw=again[1], dLdq=again[2], dLdx=again[3], deterministic=1, **kw)
+        torch.cuda.synchronize()
+        for a, b in zip((dLdG, dLdw, dLdq, dLdx), again):
+            if a is not None:
+                assert torch.equal(a, b)
     dLdG = dLdG.cpu().numpy().astype(np.float64)
     ref_G = np.zeros_like(Gref)
     ref_w = np.zeros(K)
@@ -241,6 +251,152 @@ def test_adjoint_differentiation_workload(D):
     G.say("C3 sampled: worst E/tol %.3g dLdq/tol %.3g dLdx-vs-FD/tol %.3g (%d FD poses)" % (*worst, n_fd))
     assert worst[0] <= 1.0 and worst[1] <= 1.0 and worst[2] <= 1.0
     assert n_fd >= 12
+
+
+def test_deterministic_adjoint_differentiation_workload(D):
+    """The differentiation workload (64 ligands x 32 poses, Vina-form terms):
+    two deterministic adjoints agree bit for bit in dL/dG, dL/dw, dL/dq and
+    dL/dx; the atomic mode agrees with them within FP32 summation error in
+    dL/dG and dL/dw and exactly in dL/dq and dL/dx (the intra-pair forces are
+    fixed point in both modes); node sums of dL/dG satisfy the exact
+    identity; sampled nodes match the oracle's adjoint."""
+    pk, L, wl = synth.workload("C3")
+    pk = pk[0]
+    preset, K = P.PRESET_VINA, 5
+    w = synth.vina_weights(np.random.default_rng(33))
+    p = G.load_pocket(pk, preset, w, keep=True)
+    H = G.load_ligands(L)
+    topos = [topology.from_ligands(L, i) for i in range(L.n_ligands)]
+    rng = np.random.default_rng(35)
+    T = wl["T"]
+    Q = np.zeros((L.n_ligands * T, H.q_stride), np.float32)
+    lig = np.repeat(np.arange(L.n_ligands), T).astype(np.int32)
+    for i, t in enumerate(topos):
+        Q[lig == i, :t.n_dof] = synth.random_poses(t.n_dof, t.box_min, t.box_max, T, rng)
+    c = rng.normal(size=len(Q)).astype(np.float32)
+    Gg = D.dock_pocket_maps(p, per_term=True)
+    wt = torch.tensor(w[None], device="cuda")
+    qt = torch.tensor(Q, device="cuda")
+    lt = torch.tensor(lig, device="cuda")
+    ct = torch.tensor(c, device="cuda")
+
+    def run(det):
+        out = dict(G=torch.zeros_like(Gg), w=torch.zeros_like(wt), q=torch.zeros_like(qt),
+                   x=torch.zeros((len(Q), H.max_atoms, 3), device="cuda"))
+        D.dock_score_adjoint(p, H, lt, wt, ct, q=qt, G=[Gg], dLdG=[out["G"]], dLdw=out["w"], dLdq=out["q"],
+                             dLdx=out["x"], deterministic=det)
+        torch.cuda.synchronize()
+        return out
+
+    d1, d2, a1 = run(1), run(1), run(0)
+    for k in d1:
+        assert torch.equal(d1[k], d2[k]), k
+    assert torch.equal(d1["q"], a1["q"]) and torch.equal(d1["x"], a1["x"])
+    gd, ga = d1["G"].cpu().numpy().astype(np.float64), a1["G"].cpu().numpy().astype(np.float64)
+    scale = np.abs(gd).max()
+    G.say("C3 deterministic vs atomic: dL/dG max |diff| / max %.3g, dL/dw %s vs %s"
+          % (np.abs(gd - ga).max() / scale, d1["w"].cpu().numpy(), a1["w"].cpu().numpy()))
+    assert np.abs(gd - ga).max() <= 1e-5 * scale
+    np.testing.assert_allclose(d1["w"].cpu().numpy(), a1["w"].cpu().numpy(), rtol=1e-4,
+                               atol=1e-5 * np.abs(c).sum())
+    counts = np.zeros((len(Q), 8))
+    for i, t in enumerate(topos):
+        counts[lig == i] = np.bincount(t.types, minlength=8)
+    expect = np.einsum("p,pt->t", c.astype(np.float64), counts)[:, None] * w[None].astype(np.float64)
+    got = gd.reshape(8, K, -1).sum(-1)
+    assert np.allclose(got, expect, rtol=1e-4, atol=1e-4 * np.abs(expect).max())
+    # nodes touched by a few ligands' poses, against the oracle's adjoint of
+    # exactly those poses (a separate deterministic call over them alone)
+    sub = np.flatnonzero(np.isin(lig, [0, 17, 40]))
+    xs = [FK.fk(topos[lig[j]], Q[j:j + 1, :topos[lig[j]].n_dof].astype(np.float64)) for j in sub]
+    grid = SC.grid_of(pk)
+    Gd = _lazy_terms(pk, preset, grid, xs)
+    ref = np.zeros_like(Gd)
+    for i in (0, 17, 40):
+        sel = sub[lig[sub] == i]
+        t = topos[i]
+        ref += ADJ.adjoint(Gd, w.astype(np.float64), grid, preset, t, c[sel].astype(np.float64),
+                           q=Q[sel, :t.n_dof].astype(np.float64))["dLdG"]
+    dsub = torch.zeros_like(Gg)
+    D.dock_score_adjoint(p, H, lt[sub].contiguous(), wt, ct[sub].contiguous(), q=qt[sub].contiguous(), G=[Gg],
+                         dLdG=[dsub], deterministic=1)
+    torch.cuda.synchronize()
+    dsub = dsub.cpu().numpy().astype(np.float64)
+    sc2 = np.abs(ref).max()
+    G.say("C3 subset dL/dG vs oracle: max |diff| / max %.3g" % (np.abs(dsub - ref).max() / sc2))
+    assert np.abs(dsub - ref).max() <= 1e-5 * sc2
+
+
+def _three_pockets():
+    pks = [tiny_pocket(n=30, radius=7.0, grid=32, seed=21), tiny_pocket(n=45, radius=8.0, grid=36, seed=22),
+           tiny_pocket(n=20, radius=6.0, grid=26, seed=23)]
+    return pks
+
+
+@pytest.mark.parametrize("preset", [P.PRESET_TRIDS, P.PRESET_VINA])
+def test_several_pockets_score_and_adjoint_against_oracle(D, preset):
+    """Three pockets of different sizes and grids in one call, ligands
+    assigned round-robin (ligand k -> pocket k mod 3), per-pocket weights:
+    E and dE/dq per pose, and the deterministic adjoint (dL/dG per pocket,
+    dL/dw per pocket row, dL/dq) against the oracle pocket by pocket."""
+    pks = _three_pockets()
+    K = P.n_terms(preset)
+    rng = np.random.default_rng(50 + preset)
+    W = [(np.asarray(P.default_weights(preset)) * (1 + 0.1 * rng.normal(size=K))).astype(np.float32)
+         for _ in pks]
+    ps = [G.load_pocket(pk, preset, W[i], keep=True) for i, pk in enumerate(pks)]
+    L = synth.pack_ligands([synth.make_ligand(n, t, np.random.default_rng(100 + n)) for n, t in
+                            ((6, 1), (9, 3), (12, 2), (14, 4), (8, 0), (20, 5))])
+    L.pocket_index = (np.arange(L.n_ligands) % 3).astype(np.int32)
+    H = G.load_ligands(L)
+    topos = [topology.from_ligands(L, i) for i in range(L.n_ligands)]
+    Q, lig = _poses(L, H, topos, 8, rng)
+    G.say("three pockets, preset", preset, ":", len(Q), "poses")
+    lt = torch.tensor(lig, device="cuda")
+    qt = torch.tensor(Q, device="cuda")
+    # score + gradient with each pocket's combined maps
+    E, g, _ = D.dock_score_grad(ps, H, lt, qt)
+    E, g = E.cpu().numpy(), g.cpu().numpy()
+    for i, t in enumerate(topos):
+        sel = lig == i
+        pi = int(L.pocket_index[i])
+        ref = SC.Scorer(pks[pi], preset, weights=W[pi].astype(np.float64)).score(t, Q[sel, :t.n_dof].astype(np.float64))
+        G.compare_eval(E[sel], g[sel], ref, t.n_dof, "ligand %d pocket %d" % (i, pi))
+    # differentiable form across the pockets
+    Gs = [D.dock_pocket_maps(pp, per_term=True) for pp in ps]
+    wt = torch.tensor(np.stack(W), device="cuda")
+    dLdE = rng.normal(size=len(Q)).astype(np.float32)
+    dG = [torch.zeros_like(x) for x in Gs]
+    dw = torch.zeros_like(wt)
+    dq = torch.zeros_like(qt)
+    Et = D.dock_score_terms(ps, H, lt, wt, q=qt, G=Gs).cpu().numpy()
+    D.dock_score_adjoint(ps, H, lt, wt, torch.tensor(dLdE, device="cuda"), q=qt, G=Gs, dLdG=dG, dLdw=dw, dLdq=dq,
+                         deterministic=1)
+    torch.cuda.synchronize()
+    dw, dq = dw.cpu().numpy(), dq.cpu().numpy()
+    for pi, pk in enumerate(pks):
+        grid = SC.grid_of(pk)
+        Gref = MAPS.build_maps(pk, preset)
+        refG = np.zeros_like(Gref)
+        refw = np.zeros(K)
+        for i, t in enumerate(topos):
+            if L.pocket_index[i] != pi:
+                continue
+            sel = lig == i
+            qq = Q[sel, :t.n_dof].astype(np.float64)
+            A = ADJ.adjoint(Gref, W[pi].astype(np.float64), grid, preset, t, dLdE[sel].astype(np.float64), q=qq)
+            Er = ADJ.energy(Gref, W[pi].astype(np.float64), grid, preset, t, q=qq)
+            S_abs = SC.Scorer(pk, preset, weights=W[pi].astype(np.float64), G=Gref).score(t, qq)["S_abs"]
+            assert np.all(np.abs(Et[sel] - Er) <= 1e-5 * np.maximum(np.abs(Er), S_abs))
+            refG += A["dLdG"]
+            refw += A["dLdw"]
+            err = np.linalg.norm(dq[sel, :t.n_dof] - A["dLdq"], axis=1)
+            assert np.all(err <= 1e-4 * np.linalg.norm(A["dLdq"], axis=1) + 1e-4)
+        got = dG[pi].cpu().numpy().astype(np.float64)
+        sc = np.abs(refG).max()
+        G.say("pocket %d: dL/dG max |diff| / max %.3g" % (pi, np.abs(got - refG).max() / sc))
+        assert np.abs(got - refG).max() <= 1e-5 * sc + 1e-7
+        np.testing.assert_allclose(dw[pi], refw, rtol=1e-5, atol=1e-4 * np.abs(refw).max())
 
 
 @pytest.mark.parametrize("n_rec,radius,grid", [(12, 5.0, 14), (40, 7.0, 24)])

@@ -192,6 +192,33 @@ def test_resume_and_restore_bitwise(D, mixed):
     got = _state(D, r2)
     for k in ("q_cur", "E_cur", "q_best", "E_best"):
         assert np.array_equal(full[k], got[k]), k
+    # a restarted run (created with 3 steps, advanced to 7) repeats a new
+    # 3-step run with that seed, in its own buffers
+    G.say("restart")
+    for seed in (5, 12):
+        D.dock_run_restart(r, seed)
+        _same(_state(D, D.dock_sample(p, H, n_steps=3, **dict(kw, seed=seed))), _state(D, r), ("restart", seed))
+    rp = D.dock_sample(p, H, n_steps=2, form=D.FORM_PLAIN, **kw)
+    D.dock_run_restart(rp, 31)
+    _same(_state(D, D.dock_sample(p, H, n_steps=2, form=D.FORM_PLAIN, **dict(kw, seed=31))), _state(D, rp),
+          "restart plain")
+
+
+def test_traced_subset_matches_full_trace(D, mixed):
+    """Logging only every second ligand's first three trajectories gives the
+    same rows as logging everything, in the documented block order."""
+    p, H, L, _ = mixed
+    kw = dict(n_traj=8, n_steps=3, n_local=4, seed=4, record_trace=1)
+    full = D.dock_run_state(D.dock_sample(p, H, **kw), trace=True)["trace"].cpu().numpy()
+    run = D.dock_sample(p, H, trace_lig_stride=2, trace_traj=3, **kw)
+    v = run.view()
+    assert (v.trace_lig_stride, v.trace_traj, v.n_trace) == (2, 3, 3 * ((L.n_ligands + 1) // 2))
+    sub = D.dock_run_state(run, trace=True)["trace"].cpu().numpy()
+    assert sub.shape[:2] == ((L.n_ligands + 1) // 2, 3)
+    assert np.array_equal(sub, full[::2, :3], equal_nan=True)
+    D.dock_run_restart(run, 4)
+    again = D.dock_run_state(run, trace=True)["trace"].cpu().numpy()
+    assert np.array_equal(again, sub, equal_nan=True)
 
 
 def test_trace_self_consistency(D):

@@ -30,7 +30,7 @@ def test_every_declared_symbol_is_exported():
     assert len(names) >= 20
     for n in names:
         assert hasattr(D.lib, n), n
-    assert D.dock_abi_version() == 1
+    assert D.dock_abi_version() == 2
 
 
 def _load(L, host_only=True, **kw):
