@@ -168,6 +168,11 @@ typedef struct {
   int32_t n_atoms, n_tors, n_frags, n_pairs, root, height, pocket;
   float c0[3];                 /* root-fragment centroid (FP64 mean, stored FP32) */
   float box_min[3], box_max[3];
+  /* device layout of the pair records for large batched runs: passes of
+   * pass_lanes slots (0 passes: pairs strided over the lanes), atoms per
+   * lane, entries gathered per atom and pass, and the bytes staged in LDS
+   * per work item */
+  int32_t n_pass, pass_lanes, pass_apl, pull_cap, stage_bytes;
 } dock_ligand_info_t;
 
 int dock_ligand_info(dock_ligands_t L, int32_t lig, dock_ligand_info_t* info);
@@ -311,6 +316,15 @@ int dock_autotune(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_
  * *needed (nullable) receives the size required. */
 int dock_autotune_report(char* buf, int32_t cap, int32_t* needed);
 int dock_autotune_clear(void);
+/* Puts one entry into the cache (as dock_autotune_report lists them), for
+ * restoring a cache saved from an earlier process: for natural
+ * configuration (lanes, atoms_per_lane) on architecture `arch`, run groups
+ * of chosen_lanes lanes in blocks of `block` threads.  DOCK_E_ARG unless
+ * lanes is 16/32/64, atoms_per_lane 1/2, chosen_lanes the natural width
+ * (or twice it, at most 64, with one atom per lane) and block 64/128/256
+ * holds at least one group. */
+int dock_autotune_set(const char* arch, int32_t lanes, int32_t atoms_per_lane, int32_t chosen_lanes,
+                      int32_t block, float trial_ms);
 
 /* Advances every trajectory by n_steps more MC steps (resume). */
 int dock_run_advance(dock_run_t r, int32_t n_steps, void* stream);

@@ -45,7 +45,8 @@ class LigandDesc(C.Structure):
 class LigandInfo(C.Structure):
     _fields_ = [("n_atoms", _i32), ("n_tors", _i32), ("n_frags", _i32), ("n_pairs", _i32),
                 ("root", _i32), ("height", _i32), ("pocket", _i32), ("c0", _f32 * 3),
-                ("box_min", _f32 * 3), ("box_max", _f32 * 3)]
+                ("box_min", _f32 * 3), ("box_max", _f32 * 3), ("n_pass", _i32), ("pass_lanes", _i32),
+                ("pass_apl", _i32), ("pull_cap", _i32), ("stage_bytes", _i32)]
 
 
 class SampleParams(C.Structure):
@@ -96,6 +97,7 @@ _sig("dock_run_restart", C.c_int, _p, C.c_uint32, _p)
 _sig("dock_autotune", C.c_int, _p, _i32, _p, C.POINTER(SampleParams), _i32, _p)
 _sig("dock_autotune_report", C.c_int, C.c_char_p, _i32, C.POINTER(_i32))
 _sig("dock_autotune_clear", C.c_int)
+_sig("dock_autotune_set", C.c_int, C.c_char_p, _i32, _i32, _i32, _i32, _f32)
 _sig("dock_run_view_get", C.c_int, _p, C.POINTER(RunView))
 _sig("dock_run_copy_state", C.c_int, _p, _p, _p, _p, _p, _p, _p, _p)
 _sig("dock_run_set_state", C.c_int, _p, _p, _p, _p, _p, _i32, _p)
@@ -296,7 +298,9 @@ def dock_ligand_info(L, i):
     return dict(n_atoms=info.n_atoms, n_tors=info.n_tors, n_frags=info.n_frags,
                 n_pairs=info.n_pairs, root=info.root, height=info.height, pocket=info.pocket,
                 c0=np.array(info.c0[:], np.float32), box_min=np.array(info.box_min[:], np.float32),
-                box_max=np.array(info.box_max[:], np.float32))
+                box_max=np.array(info.box_max[:], np.float32), n_pass=info.n_pass,
+                pass_lanes=info.pass_lanes, pass_apl=info.pass_apl, pull_cap=info.pull_cap,
+                stage_bytes=info.stage_bytes)
 
 
 def dock_ligand_topology(L, i):
@@ -455,6 +459,24 @@ def dock_autotune_report():
 
 def dock_autotune_clear():
     _check(lib.dock_autotune_clear())
+
+
+def dock_autotune_save(path):
+    """Writes the autotuner cache (every (arch, lanes, atoms per lane) entry)
+    to a JSON file."""
+    import json
+    with open(path, "w") as f:
+        json.dump(dock_autotune_report(), f, indent=1)
+
+
+def dock_autotune_load(path):
+    """Restores cache entries saved by dock_autotune_save; returns how many."""
+    import json
+    entries = json.load(open(path))
+    for e in entries:
+        _check(lib.dock_autotune_set(str(e["arch"]).encode(), int(e["lanes"]), int(e["atoms_per_lane"]),
+                                     int(e["chosen_lanes"]), int(e["block"]), float(e.get("trial_ms", 0.0))))
+    return len(entries)
 
 
 def dock_run_advance(run, n_steps, stream=None):

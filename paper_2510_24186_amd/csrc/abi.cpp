@@ -732,6 +732,12 @@ int dock_ligand_info(dock_ligands_t L, int32_t lig, dock_ligand_info_t* info) {
     info->box_min[c] = H.box_min[c];
     info->box_max[c] = H.box_max[c];
   }
+  const LigDev& g = L->h_ligs[lig];
+  info->n_pass = g.n_pass;
+  info->pass_lanes = g.pass_w;
+  info->pass_apl = g.pass_apl;
+  info->pull_cap = g.pull_cap;
+  info->stage_bytes = g.n_stage * int(sizeof(PairRec));
   return DOCK_OK;
 }
 
@@ -1046,8 +1052,10 @@ void dock_sample_params_default(dock_sample_params* p) {
 struct Bucket {
   int lpp = 0, apl = 0, block = 256, max_pairs = 0;
   int alt = 0;                     // ligands use their alternative pair layout
+  int per_cu = 0;                  // blocks per CU its ligands' LDS allows
   int item_off = 0, n_items = 0;   // batched: this bucket's items
   int grid = 0;                    // batched: persistent grid
+  int part_base = 0;               // batched: offset of its partition bounds in d_part
   std::vector<int> ligs;
 };
 
@@ -1062,10 +1070,14 @@ struct dock_run_s {
   int trace_stride = 1, trace_tt = 0, n_trace = 0;  // logged ligands / trajectories
   float *q_cur = nullptr, *E_cur = nullptr, *q_best = nullptr, *E_best = nullptr, *trace = nullptr;
   int* n_evals = nullptr;
-  int* d_step = nullptr;
+  int* d_step = nullptr;   // device: [0] MC steps taken, [1] seed (read by the kernels, so
+                            // graph replays follow dock_run_restart)
   int2* d_items = nullptr;
   int* d_queue = nullptr;
   int n_queue = 0;
+  int n_part = 1;                   // batched: item partitions per bucket (one per XCD for
+                                    // several pockets), each with its own queue counter
+  int* d_part = nullptr;            // per bucket: n_part + 1 item bounds
   std::vector<Bucket> buckets;
   // plain form: per ligand (bucket index, first item, item count)
   std::vector<int> lig_bucket, lig_item_off, lig_n_items;
@@ -1178,6 +1190,7 @@ static void free_run(dock_run_s* r) {
   dev_free(r->d_step);
   dev_free(r->d_items);
   dev_free(r->d_queue);
+  dev_free(r->d_part);
   delete r;
 }
 
@@ -1197,7 +1210,6 @@ static SampleArgs base_args(const dock_run_s* r) {
   a.mc_beta = r->p.mc_beta;
   a.rms_alpha = r->p.rms_alpha;
   a.weight_decay = r->p.weight_decay;
-  a.seed = r->p.seed;
   a.q_cur = r->q_cur;
   a.E_cur = r->E_cur;
   a.q_best = r->q_best;
@@ -1217,8 +1229,9 @@ static hipError_t enqueue_phase(dock_run_s* r, bool init, int steps, hipStream_t
   const int n_chunks = init ? 1 : (steps + chunk - 1) / chunk;
   hipError_t e = hipSuccess;
   const bool fork = r->p.form == DOCK_FORM_BATCHED && !r->side.empty();
+  const int nb = int(r->buckets.size()), np = r->n_part;
   if (r->p.form == DOCK_FORM_BATCHED) {
-    const int need = n_chunks * int(r->buckets.size());
+    const int need = n_chunks * nb * np;
     if (need > r->n_queue) return hipErrorInvalidValue;
     e = launch_fill_int(r->d_queue, need, 0, s);
     if (e != hipSuccess) return e;
@@ -1238,7 +1251,9 @@ static hipError_t enqueue_phase(dock_run_s* r, bool init, int steps, hipStream_t
         const Bucket& B = r->buckets[b];
         a.items = r->d_items + B.item_off;
         a.n_items = B.n_items;
-        a.queue = r->d_queue + c * int(r->buckets.size()) + int(b);
+        a.queue = r->d_queue + (c * nb + int(b)) * np;
+        a.part_off = r->d_part + B.part_base;
+        a.n_part = np;
         a.max_pairs = B.max_pairs;
         const hipStream_t bs = (fork && b > 0) ? r->side[b - 1] : s;
         e = timed_launch(r, a, int(b), B.lpp, B.apl, B.grid, B.block, bs);
@@ -1250,6 +1265,8 @@ static hipError_t enqueue_phase(dock_run_s* r, bool init, int steps, hipStream_t
         a.items = r->d_items + r->lig_item_off[l];
         a.n_items = r->lig_n_items[l];
         a.queue = nullptr;
+        a.part_off = nullptr;
+        a.n_part = 1;
         a.max_pairs = B.alt ? r->L->h_ligs[l].alt.n_stage : r->L->h_ligs[l].n_stage;
         e = timed_launch(r, a, r->lig_bucket[l], B.lpp, B.apl, r->lig_n_items[l], B.block, s);
         if (e != hipSuccess) return e;
@@ -1335,7 +1352,28 @@ static int check_params(const dock_sample_params* p) {
 struct PlanOverride {
   int nat_lpp = 0, nat_apl = 0, lpp = 0, block = 0;
   const std::vector<char>* subset = nullptr;
+  int one_per_lane = -1;  // >= 0: the full run's layout decision (trials on a subset)
 };
+
+// The layout decision of create_run: ligands of 33-64 atoms go two atoms per
+// lane when their trajectories fill at least two waves per wave slot of the
+// device with two poses per wavefront.
+static bool run_one_per_lane(const dock_ligands_s* L, int T, int n_cu, const std::vector<char>* subset) {
+  long long mid_traj = 0;
+  for (int l = 0; l < L->n; ++l) {
+    if (subset && !(*subset)[l]) continue;
+    const LigDev& g = L->h_ligs[l];
+    if (g.n_atoms <= 64 && lane_cfg(g, 0).apl == 2) mid_traj += T;
+  }
+  return mid_traj / 2 < 2LL * kWavesPerCu * n_cu;
+}
+
+static int device_cu_count() {
+  int dev = 0, n_cu = 256;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n_cu = 256;
+  return n_cu;
+}
 
 static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
                       const dock_sample_params* p, void* stream, dock_run_t* out, const PlanOverride* ov) {
@@ -1373,23 +1411,27 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
     return fail(rc, m);
   }
   // ---- plan: lane configuration per ligand, buckets, work items
-  int dev = 0, n_cu = 256;
+  int dev = 0;
   (void)hipGetDevice(&dev);
-  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n_cu = 256;
-  std::map<std::tuple<int, int, int>, int> bidx;
+  const int n_cu = device_cu_count();
+  int n_xcc = 8;
+  if (hipDeviceGetAttribute(&n_xcc, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || n_xcc < 1) n_xcc = 1;
+  // several pockets: the items of each bucket are split into one partition
+  // per XCD (pocket p -> partition p mod n_xcc), which blocks on that XCD
+  // (block b runs on XCD b mod n_xcc) take first, so that an XCD's L2 holds
+  // the maps of a few pockets instead of all of them; a block whose
+  // partition is empty takes from the others in turn
+  r->n_part = (p->form == DOCK_FORM_BATCHED && n_pockets > 1) ? std::min(n_xcc, 64) : 1;
+  std::map<std::tuple<int, int, int, int>, int> bidx;
+  std::map<std::tuple<int, int, int, int>, int> occ;  // (lpp, apl, block, LDS / 256) -> blocks per CU
   r->lig_bucket.resize(r->n_lig);
   const std::string arch = device_arch();
   // Two atoms per lane (ligands of 33-64 atoms) pays when the run fills the
   // chip many times over; a smaller run keeps one atom per lane, which gives
   // it twice the wavefronts.  The choice depends on the ligand set and the
   // trajectory count only, so every form of the run evaluates alike.
-  long long mid_traj = 0;
-  for (int l = 0; l < r->n_lig; ++l) {
-    if (ov && ov->subset && !(*ov->subset)[l]) continue;
-    const LigDev& g = L->h_ligs[l];
-    if (g.n_atoms <= 64 && lane_cfg(g, 0).apl == 2) mid_traj += r->T;
-  }
-  const bool one_per_lane = mid_traj / 2 < 2LL * kWavesPerCu * n_cu;
+  const bool one_per_lane = (ov && ov->one_per_lane >= 0) ? ov->one_per_lane != 0
+                                                            : run_one_per_lane(L, r->T, n_cu, ov ? ov->subset : nullptr);
   for (int l = 0; l < r->n_lig; ++l) {
     LaneCfg c = lane_cfg(L->h_ligs[l], p->lanes_per_pose, one_per_lane);
     int block = 256;
@@ -1406,13 +1448,28 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
         block = t->second.block;
       }
     }
-    auto key = std::make_tuple(c.lpp, c.apl, block);
+    // ligands whose staged pair records lower the blocks per CU go to a
+    // bucket of their own, so that one large ligand does not lower the
+    // occupancy of every launch of its lane configuration
+    const LigDev& gl0 = L->h_ligs[l];
+    const int stage = c.apl == 1 ? gl0.alt.n_stage : gl0.n_stage;
+    const size_t lds_l = sample_lds_bytes(c.lpp, c.apl, block, stage);
+    int per_cu = 0;
+    if (p->form == DOCK_FORM_BATCHED && lds_l <= 64 * 1024) {
+      const auto ok = std::make_tuple(c.lpp, c.apl, block, int((lds_l + 255) / 256));
+      auto oi = occ.find(ok);
+      if (oi == occ.end())
+        oi = occ.emplace(ok, sample_max_blocks_per_cu(c.lpp, c.apl, block, r->mode, (lds_l + 255) / 256 * 256)).first;
+      per_cu = oi->second;
+    }
+    auto key = std::make_tuple(c.lpp, c.apl, block, per_cu);
     auto it = bidx.find(key);
     if (it == bidx.end()) {
       Bucket B;
       B.lpp = c.lpp;
       B.apl = c.apl;
       B.block = block;
+      B.per_cu = per_cu;
       // the kernels with one atom per lane read the alternative layout (the
       // primary one for every ligand not laid out with two atoms per lane)
       B.alt = c.apl == 1 ? 1 : 0;
@@ -1426,6 +1483,7 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
     r->lig_bucket[l] = it->second;
   }
   std::vector<int2> items;
+  std::vector<int> part_bounds;  // batched: per bucket n_part + 1 bounds, relative to its items
   r->lig_item_off.assign(r->n_lig, 0);
   r->lig_n_items.assign(r->n_lig, 0);
   if (p->form == DOCK_FORM_PLAIN) {
@@ -1438,21 +1496,39 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
       r->lig_n_items[l] = int(items.size()) - r->lig_item_off[l];
     }
   } else {
+    const int np = r->n_part;
     for (Bucket& B : r->buckets) {
       const int gpb = B.block / B.lpp;
-      // longest work first: cost ~ pair slots (empty ones included) + 4 * atoms
-      // per evaluation
+      // per partition (pocket mod np), the ligands of one pocket together
+      // and, within a pocket, longest work first: cost ~ pair slots (empty
+      // ones included) + 4 * atoms per evaluation
       std::vector<int> ligs = B.ligs;
       const auto cost = [&](int l) {
         const LigDev& g = L->h_ligs[l];
         const int n_pass = B.alt ? g.alt.n_pass : g.n_pass, n_prec = B.alt ? g.alt.n_prec : g.n_prec;
         return (n_pass > 0 ? n_prec : g.n_pairs) + 4 * g.n_atoms;
       };
-      std::stable_sort(ligs.begin(), ligs.end(), [&](int x, int y) { return cost(x) > cost(y); });
+      const auto order = [&](int l) {
+        const int pk = L->h_ligs[l].pocket;
+        return std::make_tuple(np > 1 ? pk % np : 0, np > 1 ? pk : 0, -cost(l));
+      };
+      std::stable_sort(ligs.begin(), ligs.end(), [&](int x, int y) { return order(x) < order(y); });
       B.item_off = int(items.size());
+      B.part_base = int(part_bounds.size());
+      int cur = 0;
+      part_bounds.push_back(0);
       for (int l : ligs) {
         if (ov && ov->subset && !(*ov->subset)[l]) continue;
+        const int q = np > 1 ? L->h_ligs[l].pocket % np : 0;
+        while (cur < q) {
+          part_bounds.push_back(int(items.size()) - B.item_off);
+          ++cur;
+        }
         for (int t0 = 0; t0 < r->T; t0 += gpb) items.push_back(make_int2(l, t0));
+      }
+      while (cur < np) {
+        part_bounds.push_back(int(items.size()) - B.item_off);
+        ++cur;
       }
       B.n_items = int(items.size()) - B.item_off;
       const size_t lds = sample_lds_bytes(B.lpp, B.apl, B.block, B.max_pairs);
@@ -1480,15 +1556,16 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   // ---- buffers
   const size_t nt = size_t(r->n_lig) * r->T;
   const int chunk = p->steps_per_launch > 0 ? p->steps_per_launch : std::max(1, p->n_steps);
-  r->n_queue = int(r->buckets.size()) * std::max(1, (p->n_steps + chunk - 1) / chunk);
+  r->n_queue = int(r->buckets.size()) * std::max(1, (p->n_steps + chunk - 1) / chunk) * r->n_part;
   hipError_t e = dev_alloc(&r->q_cur, nt * r->q_stride);
   if (e == hipSuccess) e = dev_alloc(&r->q_best, nt * r->q_stride);
   if (e == hipSuccess) e = dev_alloc(&r->E_cur, nt);
   if (e == hipSuccess) e = dev_alloc(&r->E_best, nt);
   if (e == hipSuccess) e = dev_alloc(&r->n_evals, nt);
-  if (e == hipSuccess) e = dev_alloc(&r->d_step, 1);
+  if (e == hipSuccess) e = dev_alloc(&r->d_step, 2);
   if (e == hipSuccess) e = dev_alloc(&r->d_items, items.size());
   if (e == hipSuccess) e = dev_alloc(&r->d_queue, size_t(std::max(1, r->n_queue)));
+  if (e == hipSuccess) e = dev_alloc(&r->d_part, std::max<size_t>(1, part_bounds.size()));
   if (e == hipSuccess && p->record_trace) {
     const int per_step = p->local_opt == DOCK_LOCAL_LINESEARCH ? 1 + 11 * p->n_local : p->n_local + 1;
     r->trace_cap = 1 + p->n_steps * per_step;
@@ -1504,11 +1581,14 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
   if (e == hipSuccess) e = hipMemsetAsync(r->q_best, 0, sizeof(float) * nt * r->q_stride, s);
   if (e != hipSuccess) return bail(DOCK_E_HIP, std::string("run state clear: ") + hipGetErrorString(e));
   e = hipMemcpy(r->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !part_bounds.empty())
+    e = hipMemcpy(r->d_part, part_bounds.data(), sizeof(int) * part_bounds.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(DOCK_E_HIP, std::string("item upload: ") + hipGetErrorString(e));
   if ((e = hipEventCreate(&r->ev0)) != hipSuccess || (e = hipEventCreate(&r->ev1)) != hipSuccess)
     return bail(DOCK_E_HIP, std::string("event: ") + hipGetErrorString(e));
   e = launch_fill_int(r->n_evals, int(nt), 0, s);
   if (e == hipSuccess) e = launch_fill_int(r->d_step, 1, 0, s);
+  if (e == hipSuccess) e = launch_fill_int(r->d_step + 1, 1, int(p->seed), s);
   if (e == hipSuccess && r->trace) {
     // trace rows default to NaN
     e = hipMemsetAsync(r->trace, 0xff,
@@ -1539,10 +1619,12 @@ int dock_autotune(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_
   rc = check_params(p);
   if (rc) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  // natural lane configurations present in L
+  // natural lane configurations present in L, with the layout decision a
+  // run of all of L makes (the trials, on subsets, are held to it)
+  const bool opl = run_one_per_lane(L, p->n_traj, device_cu_count(), nullptr);
   std::map<std::pair<int, int>, std::vector<char>> nat;
   for (int l = 0; l < L->n; ++l) {
-    const LaneCfg c = lane_cfg(L->h_ligs[l], 0);
+    const LaneCfg c = lane_cfg(L->h_ligs[l], 0, opl);
     auto& m = nat[std::make_pair(c.lpp, c.apl)];
     if (m.empty()) m.assign(L->n, 0);
     m[l] = 1;
@@ -1569,6 +1651,7 @@ int dock_autotune(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_
         ov.lpp = lpp;
         ov.block = block;
         ov.subset = &kv.second;
+        ov.one_per_lane = opl ? 1 : 0;
         dock_run_t run = nullptr;
         rc = create_run(pockets, n_pockets, L, &q, stream, &run, &ov);
         if (rc) return rc;
@@ -1612,6 +1695,22 @@ int dock_autotune_report(char* buf, int32_t cap, int32_t* needed) {
   return DOCK_OK;
 }
 
+int dock_autotune_set(const char* arch, int32_t lanes, int32_t atoms_per_lane, int32_t chosen_lanes,
+                      int32_t block, float trial_ms) {
+  if (!arch || !*arch) return fail(DOCK_E_ARG, "empty architecture name");
+  const bool lanes_ok = lanes == 16 || lanes == 32 || lanes == 64;
+  if (!lanes_ok || (atoms_per_lane != 1 && atoms_per_lane != 2))
+    return fail(DOCK_E_ARG, "lanes must be 16, 32 or 64 and atoms_per_lane 1 or 2");
+  if (chosen_lanes != lanes && !(atoms_per_lane == 1 && chosen_lanes == 2 * lanes && chosen_lanes <= 64))
+    return fail(DOCK_E_ARG, "chosen_lanes must be the natural width or, with one atom per lane, twice it");
+  if ((block != 64 && block != 128 && block != 256) || block < chosen_lanes)
+    return fail(DOCK_E_ARG, "block must be 64, 128 or 256 and hold one group");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[std::make_tuple(std::string(arch), int(lanes), int(atoms_per_lane))] =
+      TuneChoice{chosen_lanes, block, std::isfinite(trial_ms) ? trial_ms : 0.f};
+  return DOCK_OK;
+}
+
 int dock_autotune_clear(void) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.clear();
@@ -1623,7 +1722,7 @@ int dock_run_advance(dock_run_t r, int32_t n_steps, void* stream) {
   if (n_steps < 0) return fail(DOCK_E_ARG, "negative n_steps");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int chunk = r->p.steps_per_launch > 0 ? r->p.steps_per_launch : std::max(1, n_steps);
-  const int need = int(r->buckets.size()) * std::max(1, (n_steps + chunk - 1) / chunk);
+  const int need = int(r->buckets.size()) * std::max(1, (n_steps + chunk - 1) / chunk) * r->n_part;
   if (need > r->n_queue) {
     dev_free(r->d_queue);
     r->n_queue = 0;
@@ -1647,6 +1746,7 @@ int dock_run_restart(dock_run_t r, uint32_t seed, void* stream) {
   // captured into a graph)
   HIP_TRY(launch_fill_int(r->n_evals, int(nt), 0, s));
   HIP_TRY(launch_fill_int(r->d_step, 1, 0, s));
+  HIP_TRY(launch_fill_int(r->d_step + 1, 1, int(seed), s));
   if (r->trace)
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(r->trace),
                             (long long)r->n_trace * r->trace_cap * (2 * r->q_stride + 1), 0xffffffffu, s));

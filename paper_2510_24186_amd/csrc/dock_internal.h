@@ -178,9 +178,12 @@ void type_pair_table(int preset, TypePair table[kTypes * kTypes]);
 // second); unused bytes name the zero entry.  Plain stores and gathers: no
 // LDS atomics.
 constexpr int kMaxPull = 8;
-// Staged bytes above which a two-atoms-per-lane ligand keeps its strided
-// pair list (8-byte records) instead of the pass layout.
-constexpr size_t kPassStageBytes = 40 * 1024;
+// Staged bytes above which a ligand of more than 64 atoms keeps its strided
+// pair list (8-byte records) instead of the pass layout: what a 256-thread
+// sampler block of four 64-lane groups (5 KiB of slab each) can add to stay
+// within 64 KiB of LDS.  The largest layouts of 65-70-atom ligands with
+// ~2,100 pairs stage ~41 KiB.
+constexpr size_t kPassStageBytes = 43 * 1024;
 struct PassPlan {
   int n_pass = 0, cap = 0, n_pull = 0;
   std::vector<int> slot_i, slot_j;

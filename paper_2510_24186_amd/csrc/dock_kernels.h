@@ -90,15 +90,17 @@ struct SampleArgs {
   const PocketDev* pockets;
   const int2* items;      // (ligand, first trajectory)
   int n_items;
-  int* queue;             // persistent work counter, or null: item = blockIdx.x
-  const int* step_base;   // device: MC steps already taken
+  int* queue;             // persistent work counters (one per partition), or null:
+                          // item = blockIdx.x
+  const int* part_off;    // n_part + 1 item bounds of the partitions
+  int n_part;             // block b takes partition b mod n_part first, then the others
+  const int* step_base;   // device: [0] MC steps already taken, [1] the seed
   int step_off;           // this launch covers steps base+off+1 .. base+off+count
   int step_count;
   int init;               // draw initial poses and score them instead of stepping
   int n_traj, q_stride;
   int n_local, local_opt;
   float lr, b1, b2, eps, mc_beta, rms_alpha, weight_decay;
-  unsigned seed;
   float* q_cur;
   float* E_cur;
   float* q_best;

@@ -562,7 +562,7 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const Pocket
                         const PairRec* pairs,
                         const GroupSlab& S, int lig, int traj, int r) {
   const size_t ti = size_t(lig) * a.n_traj + traj;
-  const uint32_t k0 = uint32_t(lig), k1 = a.seed;
+  const uint32_t k0 = uint32_t(lig), k1 = uint32_t(a.step_base[1]);
   const bool dof = r < L.n_dof;
   const int qs = a.q_stride;
   int nev = a.n_evals[ti];
@@ -711,13 +711,29 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
   const GroupSlab S = make_slab<LPP, APL>(slabs + size_t(grp) * slab_bytes(LPP, APL));
   int* s_item = reinterpret_cast<int*>(slabs + size_t(GPB) * slab_bytes(LPP, APL));
   int taken = 0;
+  // persistent: partitions in turn from the block's own (b mod n_part); a
+  // partition is left for good once its counter passes its size, so every
+  // block exits after at most n_part empty pops
+  const int home = a.queue ? int(blockIdx.x % unsigned(a.n_part)) : 0;
+  int tried = 0;
   for (;;) {
     if (threadIdx.x == 0) {
-      int it;
-      if (a.queue)
-        it = atomicAdd(a.queue, 1);
-      else
+      int it = a.n_items;
+      if (a.queue) {
+        while (tried < a.n_part) {
+          int q = home + tried;
+          if (q >= a.n_part) q -= a.n_part;
+          const int lo = a.part_off[q], n = a.part_off[q + 1] - lo;
+          const int k = n > 0 ? atomicAdd(a.queue + q, 1) : n;
+          if (k < n) {
+            it = lo + k;
+            break;
+          }
+          ++tried;
+        }
+      } else {
         it = taken == 0 ? int(blockIdx.x) : a.n_items;
+      }
       *s_item = it;
     }
     __syncthreads();

@@ -133,3 +133,23 @@ def test_noalloc_rank_refuses_sizes_beyond_its_scratch():
     assert f(fake, 10, 1, 1025, fake, fake, None) == -1
     assert f(fake, 10, 1, 8, None, fake, None) == -1
     assert f(fake, -1, 1, 8, fake, fake, None) == -1
+
+
+def test_autotune_cache_saved_and_restored(tmp_path):
+    # no device work: the cache is host state
+    D.dock_autotune_clear()
+    assert D.dock_autotune_report() == []
+    D.lib.dock_autotune_set(b"gfx950", 32, 2, 32, 128, 1.5)
+    assert D.lib.dock_autotune_set(b"gfx950", 16, 1, 32, 256, 2.0) == 0
+    assert D.lib.dock_autotune_set(b"gfx950", 32, 2, 64, 256, 1.0) == -1   # two per lane keeps its width
+    assert D.lib.dock_autotune_set(b"gfx950", 64, 1, 64, 32, 1.0) == -1    # block smaller than a group
+    assert D.lib.dock_autotune_set(b"", 64, 1, 64, 64, 1.0) == -1
+    before = D.dock_autotune_report()
+    path = str(tmp_path / "tune.json")
+    D.dock_autotune_save(path)
+    D.dock_autotune_clear()
+    assert D.dock_autotune_load(path) == 2
+    assert D.dock_autotune_report() == before
+    assert {(e["lanes"], e["atoms_per_lane"], e["chosen_lanes"], e["block"]) for e in before} == \
+        {(32, 2, 32, 128), (16, 1, 32, 256)}
+    D.dock_autotune_clear()
