@@ -340,6 +340,12 @@ def main():
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--workers", type=int, default=None,
+                    help="processes drawing the synthetic inputs (1: in this process, e.g. under a profiler)")
+    ap.add_argument("--inputs", default=None,
+                    help="file of drawn inputs: loaded when it exists, else written after drawing")
+    ap.add_argument("--extras-only", default="workloads,differentiation,modes",
+                    help="comma list of side measurements to run (workloads, differentiation, modes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the sampler has no multi-GPU path (ligands and "
@@ -347,11 +353,22 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     name = args.workload
-    workers = synth.default_workers()
+    workers = synth.default_workers() if args.workers is None else max(1, args.workers)
     # inputs are drawn before the GPU is touched (the drawing pool forks no
     # process that holds the device)
     t0 = time.perf_counter()
-    pks, L, wl = synth.workload(name, workers=workers)
+    if args.inputs and os.path.exists(args.inputs):
+        import pickle
+        with open(args.inputs, "rb") as f:
+            saved = pickle.load(f)   # written by this script (below)
+        assert saved[0] == name, "inputs file holds another workload"
+        pks, L, wl = saved[1:]
+    else:
+        pks, L, wl = synth.workload(name, workers=workers)
+        if args.inputs:
+            import pickle
+            with open(args.inputs, "wb") as f:
+                pickle.dump((name, pks, L, wl), f)
     print("workload %s drawn in %.1fs" % (name, time.perf_counter() - t0), file=sys.stderr, flush=True)
 
     import torch
@@ -425,7 +442,7 @@ def main():
     dom = max(per_bucket.values(), key=lambda d: d["flop"])
     launch_ms = float(np.mean(dom["ms"]))
     achieved = dom["flop"] / (launch_ms * 1e-3) / 1e12
-    kkey = "%d,%d,%d" % (dom["lanes"], dom["apl"], dom["block"])
+    kkey = "%d,%d,%d,%d" % (dom["lanes"], dom["apl"], dom["block"], dom["grid"])
     rec = kernel_record(name, kkey)
     sampler_ms = float(np.mean(kern_ms))
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
@@ -483,11 +500,15 @@ def main():
         print("plain form: %.1f ligands/s" % pr["ligands_per_s"], file=sys.stderr, flush=True)
     if not args.no_extras:
         ex = {}
-        others = [w for w in ("C4", "C2") if w != name]
-        ex["workloads"] = {w: workload_rate(D, w, workers=workers) for w in others}
-        print("other workloads done", file=sys.stderr, flush=True)
-        ex["differentiation"] = differentiation_rate(D)
-        ex.update(extras(D, pks[0], L, T, S))
+        which = set(args.extras_only.split(","))
+        if "workloads" in which:
+            others = [w for w in ("C4", "C2") if w != name]
+            ex["workloads"] = {w: workload_rate(D, w, workers=workers) for w in others}
+            print("other workloads done", file=sys.stderr, flush=True)
+        if "differentiation" in which:
+            ex["differentiation"] = differentiation_rate(D)
+        if "modes" in which:
+            ex.update(extras(D, pks[0], L, T, S))
         out["extras"] = ex
         print("extras done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
