@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <mutex>
 #include <new>
@@ -27,6 +28,30 @@ static thread_local std::string g_err;
 
 static int fail(int code, const std::string& msg) {
   g_err = msg;
+  return code;
+}
+
+// Status of an exception caught at an entry point (every exported function
+// with a body is a function-try-block, so none escapes into C callers): a
+// failed host allocation is DOCK_E_OOM, a size the standard containers
+// refuse is DOCK_E_ARG.  Called only from a catch handler.
+static int exception_status() noexcept {
+  int code = DOCK_E_ARG;
+  const char* what = "unknown exception";
+  try {
+    throw;
+  } catch (const std::bad_alloc&) {
+    code = DOCK_E_OOM;
+    what = "host allocation failed";
+  } catch (const std::exception& e) {
+    what = e.what();
+  } catch (...) {
+  }
+  try {
+    g_err = what;
+  } catch (...) {
+    g_err.clear();
+  }
   return code;
 }
 
@@ -212,7 +237,7 @@ int dock_abi_version(void) { return DOCK_ABI_VERSION; }
 
 // ================================================================ pocket
 
-int dock_load_pocket(const dock_pocket_desc* d, void* stream, dock_pocket_t* out) {
+int dock_load_pocket(const dock_pocket_desc* d, void* stream, dock_pocket_t* out) try {
   if (!d || !out) return fail(DOCK_E_ARG, "null argument");
   if (d->n_atoms < 0 || (d->n_atoms > 0 && (!d->xyz || !d->type)))
     return fail(DOCK_E_ARG, "bad receptor arrays");
@@ -380,16 +405,20 @@ int dock_load_pocket(const dock_pocket_desc* d, void* stream, dock_pocket_t* out
   pd.G = p->d_G;
   *out = p;
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_pocket_rebuild(dock_pocket_t p, void* stream) {
+int dock_pocket_rebuild(dock_pocket_t p, void* stream) try {
   if (!p) return fail(DOCK_E_ARG, "null pocket");
   if (p->dev.inter_mode != DOCK_INTER_GRID) return DOCK_OK;  // direct mode: no maps
   HIP_TRY(launch_map_build(p->build, reinterpret_cast<hipStream_t>(stream)));
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_pocket_maps(dock_pocket_t p, int32_t per_term, float** dev_ptr, int64_t* n_floats) {
+int dock_pocket_maps(dock_pocket_t p, int32_t per_term, float** dev_ptr, int64_t* n_floats) try {
   if (!p || !dev_ptr) return fail(DOCK_E_ARG, "null argument");
   if (p->dev.inter_mode == DOCK_INTER_DIRECT) return fail(DOCK_E_ARG, "a direct-mode pocket has no maps");
   const long long nodes = (long long)p->dev.grid.dims[0] * p->dev.grid.dims[1] * p->dev.grid.dims[2];
@@ -402,9 +431,11 @@ int dock_pocket_maps(dock_pocket_t p, int32_t per_term, float** dev_ptr, int64_t
     if (n_floats) *n_floats = (long long)kTypes * nodes;
   }
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_pocket_copy_maps(dock_pocket_t p, int32_t per_term, float* dst, void* stream) {
+int dock_pocket_copy_maps(dock_pocket_t p, int32_t per_term, float* dst, void* stream) try {
   float* src = nullptr;
   int64_t n = 0;
   int rc = dock_pocket_maps(p, per_term, &src, &n);
@@ -413,18 +444,22 @@ int dock_pocket_copy_maps(dock_pocket_t p, int32_t per_term, float* dst, void* s
   HIP_TRY(hipMemcpyAsync(dst, src, size_t(n) * sizeof(float), hipMemcpyDeviceToDevice,
                          reinterpret_cast<hipStream_t>(stream)));
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_pocket_terms(dock_pocket_t p, int32_t* preset, int32_t* n_terms, float* weights) {
+int dock_pocket_terms(dock_pocket_t p, int32_t* preset, int32_t* n_terms, float* weights) try {
   if (!p) return fail(DOCK_E_ARG, "null pocket");
   if (preset) *preset = p->dev.preset;
   if (n_terms) *n_terms = p->dev.n_terms;
   if (weights)
     for (int k = 0; k < p->dev.n_terms; ++k) weights[k] = p->dev.w[k];
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_free_pocket(dock_pocket_t p) {
+int dock_free_pocket(dock_pocket_t p) try {
   if (!p) return DOCK_OK;
   if (p->n_runs.load() > 0)
     return fail(DOCK_E_ARG, "pocket is still used by " + std::to_string(p->n_runs.load()) +
@@ -434,6 +469,8 @@ int dock_free_pocket(dock_pocket_t p) {
   free_pocket_device(p);
   delete p;
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 // ================================================================ ligands
@@ -456,7 +493,7 @@ static int bit_length(int v) {
   return b;
 }
 
-int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* out) {
+int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* out) try {
   (void)stream;
   if (!d || !out) return fail(DOCK_E_ARG, "null argument");
   if (d->n_ligands < 1) return fail(DOCK_E_ARG, "n_ligands must be >= 1");
@@ -714,9 +751,11 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
   }
   *out = L;
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_ligand_info(dock_ligands_t L, int32_t lig, dock_ligand_info_t* info) {
+int dock_ligand_info(dock_ligands_t L, int32_t lig, dock_ligand_info_t* info) try {
   if (!L || !info) return fail(DOCK_E_ARG, "null argument");
   if (lig < 0 || lig >= L->n) return fail(DOCK_E_ARG, "ligand index out of range");
   const LigandHost& H = L->host[lig];
@@ -739,11 +778,13 @@ int dock_ligand_info(dock_ligands_t L, int32_t lig, dock_ligand_info_t* info) {
   info->pull_cap = g.pull_cap;
   info->stage_bytes = g.n_stage * int(sizeof(PairRec));
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 int dock_ligand_topology(dock_ligands_t L, int32_t lig, uint8_t* type, int32_t* atom_frag,
                          int32_t* frag_parent, int32_t* tors_frag, int32_t* tors_atoms, int32_t* pairs,
-                         int32_t* bfs) {
+                         int32_t* bfs) try {
   if (!L) return fail(DOCK_E_ARG, "null argument");
   if (lig < 0 || lig >= L->n) return fail(DOCK_E_ARG, "ligand index out of range");
   const LigandHost& H = L->host[lig];
@@ -763,9 +804,11 @@ int dock_ligand_topology(dock_ligands_t L, int32_t lig, uint8_t* type, int32_t* 
     }
   if (bfs) std::copy(H.bfs.begin(), H.bfs.end(), bfs);
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_ligands_set_mdn(dock_ligands_t L, int32_t n_res, int32_t n_gauss, const float* params) {
+int dock_ligands_set_mdn(dock_ligands_t L, int32_t n_res, int32_t n_gauss, const float* params) try {
   if (!L || !params) return fail(DOCK_E_ARG, "null argument");
   if (L->host_only) return fail(DOCK_E_ARG, "ligand handle was loaded host_only");
   if (n_res < 1 || n_gauss < 1 || n_gauss > 16) return fail(DOCK_E_ARG, "n_res >= 1 and 1 <= n_gauss <= 16");
@@ -800,19 +843,23 @@ int dock_ligands_set_mdn(dock_ligands_t L, int32_t n_res, int32_t n_gauss, const
   L->mdn_res = n_res;
   L->mdn_k = n_gauss;
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 int dock_ligands_count(dock_ligands_t L, int32_t* n_ligands, int32_t* max_atoms, int32_t* max_tors,
-                       int64_t* total_atoms) {
+                       int64_t* total_atoms) try {
   if (!L) return fail(DOCK_E_ARG, "null argument");
   if (n_ligands) *n_ligands = L->n;
   if (max_atoms) *max_atoms = L->max_atoms;
   if (max_tors) *max_tors = L->max_tors;
   if (total_atoms) *total_atoms = L->total_atoms;
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_free_ligands(dock_ligands_t L) {
+int dock_free_ligands(dock_ligands_t L) try {
   if (!L) return DOCK_OK;
   if (L->n_runs.load() > 0)
     return fail(DOCK_E_ARG, "ligand handle is still used by " + std::to_string(L->n_runs.load()) +
@@ -821,6 +868,8 @@ int dock_free_ligands(dock_ligands_t L) {
   free_ligand_device(L);
   delete L;
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 // ================================================================ score
@@ -856,7 +905,7 @@ static int eval_mode(const dock_pocket_t* pockets, int n_pockets, dock_ligands_t
 
 int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L, int64_t n_poses,
                     const int32_t* pose_lig, const float* q, int32_t q_stride, float* E, float* dEdq,
-                    float* xyz_out, int32_t xyz_stride, void* stream) {
+                    float* xyz_out, int32_t xyz_stride, void* stream) try {
   if (!L) return fail(DOCK_E_ARG, "null ligands");
   int rc = check_pockets(pockets, n_pockets, L);
   if (rc) return rc;
@@ -889,6 +938,8 @@ int dock_score_grad(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligand
   HIP_TRY(launch_score(a, lpp, apl, eval_mode(pockets, n_pockets, L),
                        reinterpret_cast<hipStream_t>(stream)));
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 // ================================================================ differentiable form
@@ -1008,21 +1059,25 @@ static int terms_call(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
 
 int dock_score_terms(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L, int64_t n_poses,
                      const int32_t* pose_lig, const float* q, int32_t q_stride, const float* xyz,
-                     int32_t xyz_stride, const float* const* G, const float* w, float* E, void* stream) {
+                     int32_t xyz_stride, const float* const* G, const float* w, float* E, void* stream) try {
   if (!E) return fail(DOCK_E_ARG, "null E");
   return terms_call(pockets, n_pockets, L, n_poses, pose_lig, q, q_stride, xyz, xyz_stride, G, w, E, nullptr,
                     nullptr, nullptr, nullptr, nullptr, 0, stream);
+} catch (...) {
+  return exception_status();
 }
 
 int dock_score_adjoint(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L, int64_t n_poses,
                        const int32_t* pose_lig, const float* q, int32_t q_stride, const float* xyz,
                        int32_t xyz_stride, const float* const* G, const float* w, const float* dLdE,
                        float* const* dLdG, float* dLdw, float* dLdq, float* dLdx, int32_t deterministic,
-                       void* stream) {
+                       void* stream) try {
   if (!dLdE) return fail(DOCK_E_ARG, "null dLdE");
   if (deterministic != 0 && deterministic != 1) return fail(DOCK_E_ARG, "deterministic must be 0 or 1");
   return terms_call(pockets, n_pockets, L, n_poses, pose_lig, q, q_stride, xyz, xyz_stride, G, w, nullptr, dLdE,
                     dLdG, dLdw, dLdq, dLdx, deterministic, stream);
+} catch (...) {
+  return exception_status();
 }
 
 // ================================================================ sampling
@@ -1606,12 +1661,14 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
 }
 
 int dock_sample(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
-                const dock_sample_params* p, void* stream, dock_run_t* out) {
+                const dock_sample_params* p, void* stream, dock_run_t* out) try {
   return create_run(pockets, n_pockets, L, p, stream, out, nullptr);
+} catch (...) {
+  return exception_status();
 }
 
 int dock_autotune(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_t L,
-                  const dock_sample_params* p, int32_t trial_steps, void* stream) {
+                  const dock_sample_params* p, int32_t trial_steps, void* stream) try {
   if (!L || !p) return fail(DOCK_E_ARG, "null argument");
   if (trial_steps < 1) return fail(DOCK_E_ARG, "trial_steps must be >= 1");
   int rc = check_pockets(pockets, n_pockets, L);
@@ -1667,9 +1724,11 @@ int dock_autotune(const dock_pocket_t* pockets, int32_t n_pockets, dock_ligands_
   }
   HIP_TRY(hipStreamSynchronize(s));
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_autotune_report(char* buf, int32_t cap, int32_t* needed) {
+int dock_autotune_report(char* buf, int32_t cap, int32_t* needed) try {
   std::string out = "[";
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1693,10 +1752,12 @@ int dock_autotune_report(char* buf, int32_t cap, int32_t* needed) {
     buf[cap - 1] = 0;
   }
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 int dock_autotune_set(const char* arch, int32_t lanes, int32_t atoms_per_lane, int32_t chosen_lanes,
-                      int32_t block, float trial_ms) {
+                      int32_t block, float trial_ms) try {
   if (!arch || !*arch) return fail(DOCK_E_ARG, "empty architecture name");
   const bool lanes_ok = lanes == 16 || lanes == 32 || lanes == 64;
   if (!lanes_ok || (atoms_per_lane != 1 && atoms_per_lane != 2))
@@ -1709,15 +1770,19 @@ int dock_autotune_set(const char* arch, int32_t lanes, int32_t atoms_per_lane, i
   g_tune[std::make_tuple(std::string(arch), int(lanes), int(atoms_per_lane))] =
       TuneChoice{chosen_lanes, block, std::isfinite(trial_ms) ? trial_ms : 0.f};
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_autotune_clear(void) {
+int dock_autotune_clear(void) try {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.clear();
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_run_advance(dock_run_t r, int32_t n_steps, void* stream) {
+int dock_run_advance(dock_run_t r, int32_t n_steps, void* stream) try {
   if (!r) return fail(DOCK_E_ARG, "null run");
   if (n_steps < 0) return fail(DOCK_E_ARG, "negative n_steps");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1735,9 +1800,11 @@ int dock_run_advance(dock_run_t r, int32_t n_steps, void* stream) {
     r->graph_steps = -1;
   }
   return timed_phases(r, false, n_steps, s);
+} catch (...) {
+  return exception_status();
 }
 
-int dock_run_restart(dock_run_t r, uint32_t seed, void* stream) {
+int dock_run_restart(dock_run_t r, uint32_t seed, void* stream) try {
   if (!r) return fail(DOCK_E_ARG, "null run");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t nt = size_t(r->n_lig) * r->T;
@@ -1753,9 +1820,11 @@ int dock_run_restart(dock_run_t r, uint32_t seed, void* stream) {
   r->p.seed = seed;
   r->step = 0;
   return timed_phases(r, true, r->p.n_steps, s);
+} catch (...) {
+  return exception_status();
 }
 
-int dock_run_view_get(dock_run_t r, dock_run_view* v) {
+int dock_run_view_get(dock_run_t r, dock_run_view* v) try {
   if (!r || !v) return fail(DOCK_E_ARG, "null argument");
   v->n_ligands = r->n_lig;
   v->n_traj = r->T;
@@ -1772,10 +1841,12 @@ int dock_run_view_get(dock_run_t r, dock_run_view* v) {
   v->trace_traj = r->trace_tt;
   v->n_trace = r->n_trace;
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 int dock_run_copy_state(dock_run_t r, float* q_cur, float* E_cur, float* q_best, float* E_best,
-                        int32_t* n_evals, float* trace, void* stream) {
+                        int32_t* n_evals, float* trace, void* stream) try {
   if (!r) return fail(DOCK_E_ARG, "null run");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t nt = size_t(r->n_lig) * r->T;
@@ -1791,10 +1862,12 @@ int dock_run_copy_state(dock_run_t r, float* q_cur, float* E_cur, float* q_best,
                            D2D, s));
   }
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 int dock_run_set_state(dock_run_t r, const float* q_cur, const float* E_cur, const float* q_best,
-                       const float* E_best, int32_t step, void* stream) {
+                       const float* E_best, int32_t step, void* stream) try {
   if (!r || !q_cur || !E_cur || !q_best || !E_best) return fail(DOCK_E_ARG, "null argument");
   if (step < 0) return fail(DOCK_E_ARG, "negative step");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1806,17 +1879,21 @@ int dock_run_set_state(dock_run_t r, const float* q_cur, const float* E_cur, con
   HIP_TRY(launch_fill_int(r->d_step, 1, step, s));
   r->step = step;
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_run_kernel_ms(dock_run_t r, float* ms) {
+int dock_run_kernel_ms(dock_run_t r, float* ms) try {
   if (!r || !ms) return fail(DOCK_E_ARG, "null argument");
   if (!r->timed) return fail(DOCK_E_ARG, "run has no timed launches");
   HIP_TRY(hipEventSynchronize(r->ev1));
   HIP_TRY(hipEventElapsedTime(ms, r->ev0, r->ev1));
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_run_launch_stats(dock_run_t r, dock_launch_stat* out, int32_t cap, int32_t* n) {
+int dock_run_launch_stats(dock_run_t r, dock_launch_stat* out, int32_t cap, int32_t* n) try {
   if (!r || !n) return fail(DOCK_E_ARG, "null argument");
   if (!r->launches.empty()) HIP_TRY(hipEventSynchronize(r->launches.back().b));
   int k = 0;
@@ -1831,10 +1908,12 @@ int dock_run_launch_stats(dock_run_t r, dock_launch_stat* out, int32_t cap, int3
   }
   *n = k;
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 int dock_run_plan(dock_run_t r, int32_t* lig_bucket, int32_t* bucket_lanes, int32_t* bucket_apl,
-                  int32_t* n_buckets) {
+                  int32_t* n_buckets) try {
   if (!r) return fail(DOCK_E_ARG, "null run");
   if (lig_bucket)
     for (int l = 0; l < r->n_lig; ++l) lig_bucket[l] = r->lig_bucket[l];
@@ -1844,13 +1923,17 @@ int dock_run_plan(dock_run_t r, int32_t* lig_bucket, int32_t* bucket_lanes, int3
   }
   if (n_buckets) *n_buckets = int(r->buckets.size());
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
-int dock_free_run(dock_run_t r) {
+int dock_free_run(dock_run_t r) try {
   if (!r) return DOCK_OK;
   (void)hipDeviceSynchronize();
   free_run(r);
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 // ================================================================ best poses
@@ -1858,7 +1941,7 @@ int dock_free_run(dock_run_t r) {
 int dock_best_poses(dock_ligands_t L, int32_t n_traj, const float* E_best, const float* q_best,
                     int32_t q_stride, int32_t top_n, float rmsd_cluster, float w_tor, float* E_out,
                     float* E_screen, float* q_out, int32_t* idx_out, float* xyz_out, int32_t xyz_stride,
-                    int32_t* n_out, void* stream) {
+                    int32_t* n_out, void* stream) try {
   if (!L) return fail(DOCK_E_ARG, "null ligands");
   if (L->host_only) return fail(DOCK_E_ARG, "ligand handle was loaded host_only");
   if (n_traj < 1 || n_traj > 8192) return fail(DOCK_E_ARG, "n_traj must be in [1, 8192]");
@@ -1891,10 +1974,12 @@ int dock_best_poses(dock_ligands_t L, int32_t n_traj, const float* E_best, const
     return fail(DOCK_E_LIMIT, "n_traj * top_n too large for the best-pose LDS budget");
   HIP_TRY(launch_best(a, reinterpret_cast<hipStream_t>(stream)));
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 int dock_pocket_map_adjoint(dock_pocket_t p, const float* dLdG, float* dLdxyz, double* dLdtheta,
-                            void* stream) {
+                            void* stream) try {
   if (!p || !dLdG) return fail(DOCK_E_ARG, "null argument");
   if (p->dev.inter_mode != DOCK_INTER_GRID || !p->d_rec)
     return fail(DOCK_E_ARG, "the map adjoint needs a grid-mode pocket");
@@ -1909,6 +1994,8 @@ int dock_pocket_map_adjoint(dock_pocket_t p, const float* dLdG, float* dLdxyz, d
   a.dLdtheta = dLdtheta;
   HIP_TRY(launch_map_adjoint(a, reinterpret_cast<hipStream_t>(stream)));
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 // The rank passes of dock_screen_rank: each keeps top_k of every block of
@@ -1954,7 +2041,7 @@ static int check_rank_args(const float* scores, int64_t n, int32_t stride, int32
 }
 
 int dock_screen_rank(const float* scores, int64_t n, int32_t stride, int32_t top_k, float* score_out,
-                     int32_t* lig_out, void* stream) {
+                     int32_t* lig_out, void* stream) try {
   int rc = check_rank_args(scores, n, stride, top_k, score_out, lig_out);
   if (rc) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1976,6 +2063,8 @@ int dock_screen_rank(const float* scores, int64_t n, int32_t stride, int32_t top
   }
   if (e != hipSuccess) return fail(DOCK_E_HIP, hipGetErrorString(e));
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 // Scratch of dock_screen_rank_noalloc: the two ping-pong buffer pairs
@@ -2008,7 +2097,7 @@ static int noalloc_scratch(unsigned char** out) {
 }
 
 int dock_screen_rank_noalloc(const float* scores, int64_t n, int32_t stride, int32_t top_k, float* score_out,
-                             int32_t* lig_out, void* stream) {
+                             int32_t* lig_out, void* stream) try {
   int rc = check_rank_args(scores, n, stride, top_k, score_out, lig_out);
   if (rc) return rc;
   const long long blocks0 = (n + kRankBlock - 1) / kRankBlock;
@@ -2026,14 +2115,18 @@ int dock_screen_rank_noalloc(const float* scores, int64_t n, int32_t stride, int
                                    reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(DOCK_E_HIP, hipGetErrorString(e));
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 int dock_philox(const uint32_t* counters, uint32_t k0, uint32_t k1, int64_t n, uint32_t* out,
-                void* stream) {
+                void* stream) try {
   if (n < 0) return fail(DOCK_E_ARG, "negative n");
   if (n > 0 && (!counters || !out)) return fail(DOCK_E_ARG, "null array");
   HIP_TRY(launch_philox(counters, k0, k1, n, out, reinterpret_cast<hipStream_t>(stream)));
   return DOCK_OK;
+} catch (...) {
+  return exception_status();
 }
 
 }  // extern "C"
