@@ -196,8 +196,9 @@ def _event_ms(fn):
     return a.elapsed_time(b), res
 
 
-def workload_rate(D, name, steps=1, workers=1):
-    """One untimed and `steps` timed whole steps of a one-pocket workload."""
+def workload_rate(D, name, steps=1, workers=1, plain=False):
+    """One untimed and `steps` timed whole steps of a one-pocket workload;
+    with `plain`, also the plain form over all of its ligands."""
     import torch
     pks, L, wl = synth.workload(name, workers=workers)
     H = D.dock_load_ligands(L.atom_off, L.element, L.n_h, L.xyz, L.bond_off, L.bonds, L.rotatable,
@@ -213,9 +214,38 @@ def workload_rate(D, name, steps=1, workers=1):
     ms = 1e3 * (time.perf_counter() - t0) / steps
     ev = H.n * T * (1 + S * (N_LOCAL + 1))
     kms = D.dock_run_kernel_ms(step.run)
-    return dict(ligands=H.n, n_traj=T, n_steps=S, ms_per_step=round(ms, 2),
-                evals_per_s=round(ev / (ms * 1e-3), 1), ligands_per_s=round(H.n / (ms * 1e-3), 1),
-                sampler_ms=round(kms, 2))
+    out = dict(ligands=H.n, n_traj=T, n_steps=S, ms_per_step=round(ms, 2),
+               evals_per_s=round(ev / (ms * 1e-3), 1), ligands_per_s=round(H.n / (ms * 1e-3), 1),
+               sampler_ms=round(kms, 2))
+    if plain:
+        # both forms timed alike: sampling from a new run, best poses
+        forms = {}
+        for fname, form in (("batched", D.FORM_BATCHED), ("plain", D.FORM_PLAIN)):
+            fms = _form_ms(D, step.pockets, H, T, S, form)
+            forms[fname] = dict(ms=round(fms, 2), evals_per_s=round(ev / (fms * 1e-3), 1),
+                                ligands_per_s=round(H.n / (fms * 1e-3), 2))
+        out["forms"] = forms
+        out["batched_vs_plain"] = round(forms["plain"]["ms"] / forms["batched"]["ms"], 3)
+    return out
+
+
+def _form_ms(D, pockets, H, T, S, form):
+    """Wall time of one dock_sample call of the given form (the plain form:
+    one launch per ligand, in order, on one stream) over every ligand of H,
+    best poses included, after a one-step warm-up."""
+    import torch
+    D.dock_sample(pockets, H, n_traj=T, n_steps=1, n_local=N_LOCAL, seed=3, form=form, use_graph=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run = D.dock_sample(pockets, H, n_traj=T, n_steps=S, n_local=N_LOCAL, seed=0, form=form, use_graph=0)
+    v = run.view()
+    E_best = torch.empty((v.n_ligands, v.n_traj), device="cuda")
+    q_best = torch.empty((v.n_ligands, v.n_traj, v.q_stride), device="cuda")
+    D.lib.dock_run_copy_state(run.handle, None, None, D.binding._dptr(q_best), D.binding._dptr(E_best),
+                              None, None, D.binding._stream(None))
+    D.dock_best_poses(H, T, E_best, q_best, top_n=8, want_xyz=True)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0)
 
 
 def differentiation_rate(D):
@@ -300,25 +330,13 @@ def extras(D, pk, L, T, S, n_sub=32):
 def plain_rate(D, pks, L, H_full, T, S, n_sub=256):
     """The plain form (one launch per ligand, in order, on one stream) on a
     size-stratified subset of the workload, all pockets in the call."""
-    import torch
     order = np.argsort(np.diff(L.atom_off), kind="stable")
     sub = np.sort(order[np.linspace(0, len(order) - 1, min(n_sub, L.n_ligands)).astype(int)])
     Ls = L.subset(sub)
     Hs = D.dock_load_ligands(Ls.atom_off, Ls.element, Ls.n_h, Ls.xyz, Ls.bond_off, Ls.bonds, Ls.rotatable,
                              pocket_index=Ls.pocket_index)
     pockets = load_pockets(D, pks, False)
-    D.dock_sample(pockets, Hs, n_traj=T, n_steps=1, n_local=N_LOCAL, seed=3, form=D.FORM_PLAIN, use_graph=0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run = D.dock_sample(pockets, Hs, n_traj=T, n_steps=S, n_local=N_LOCAL, seed=0, form=D.FORM_PLAIN, use_graph=0)
-    v = run.view()
-    E_best = torch.empty((v.n_ligands, v.n_traj), device="cuda")
-    q_best = torch.empty((v.n_ligands, v.n_traj, v.q_stride), device="cuda")
-    D.lib.dock_run_copy_state(run.handle, None, None, D.binding._dptr(q_best), D.binding._dptr(E_best),
-                              None, None, D.binding._stream(None))
-    D.dock_best_poses(Hs, T, E_best, q_best, top_n=8, want_xyz=True)
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0)
+    ms = _form_ms(D, pockets, Hs, T, S, D.FORM_PLAIN)
     ev = len(sub) * T * (1 + S * (N_LOCAL + 1))
     return dict(ligands=len(sub), subset="stratified by size", ms=round(ms, 2),
                 evals_per_s=round(ev / (ms * 1e-3), 1), ligands_per_s=round(len(sub) / (ms * 1e-3), 2))
@@ -502,8 +520,8 @@ def main():
         ex = {}
         which = set(args.extras_only.split(","))
         if "workloads" in which:
-            others = [w for w in ("C4", "C2") if w != name]
-            ex["workloads"] = {w: workload_rate(D, w, workers=workers) for w in others}
+            others = [w for w in ("C4", "C2", "C1") if w != name]
+            ex["workloads"] = {w: workload_rate(D, w, workers=workers, plain=w in ("C2", "C1")) for w in others}
             print("other workloads done", file=sys.stderr, flush=True)
         if "differentiation" in which:
             ex["differentiation"] = differentiation_rate(D)
