@@ -248,6 +248,37 @@ def _form_ms(D, pockets, H, T, S, form):
     return 1e3 * (time.perf_counter() - t0)
 
 
+def paper_shape_rate(D, n_single=8):
+    """Dockings in the paper's sampling shape (1,024 copies x 8 MC steps x
+    10 Adam steps per ligand; Methods, "Conformation sampling") on the
+    screening workload's pocket and ligands: single mode, one ligand per
+    call (mean over `n_single` ligands spread over the size range), and
+    batch mode, all 256 ligands in one call.  Sampling plus best poses,
+    wall time.  Context for the paper's per-docking times (Table 5), which
+    were taken on other hardware with a pipeline that includes more than
+    this path."""
+    pks, L, wl = synth.workload("C2")
+    T, S = 1024, 8
+    pockets = load_pockets(D, pks, False)
+    H = D.dock_load_ligands(L.atom_off, L.element, L.n_h, L.xyz, L.bond_off, L.bonds, L.rotatable,
+                            pocket_index=L.pocket_index)
+    order = np.argsort(np.diff(L.atom_off), kind="stable")
+    pick = np.sort(order[np.linspace(0, len(order) - 1, n_single).astype(int)])
+    single = []
+    for i in pick:
+        Li = L.subset(np.array([i]))
+        Hi = D.dock_load_ligands(Li.atom_off, Li.element, Li.n_h, Li.xyz, Li.bond_off, Li.bonds, Li.rotatable,
+                                 pocket_index=Li.pocket_index)
+        single.append(_form_ms(D, pockets, Hi, T, S, D.FORM_BATCHED))
+    batch = _form_ms(D, pockets, H, T, S, D.FORM_BATCHED)
+    ev = T * (1 + S * (N_LOCAL + 1))
+    return dict(n_traj=T, n_steps=S, n_local=N_LOCAL, evals_per_docking=ev,
+                single_ms_per_docking=round(float(np.mean(single)), 3), single_ligands=int(len(pick)),
+                batch_ligands=H.n, batch_ms=round(batch, 2), batch_ms_per_pair=round(batch / H.n, 4),
+                batch_evals_per_s=round(ev * H.n / (batch * 1e-3), 1),
+                paper_context="Table 5 (RTX A6000, whole pipeline): 2.3 s per docking single, 0.33 s per pair batch")
+
+
 def differentiation_rate(D):
     """The differentiation workload (2,000-atom pocket, Vina-form terms, 64
     ligands x 32 poses): forward (dock_score_terms) and adjoint
@@ -362,8 +393,9 @@ def main():
                     help="processes drawing the synthetic inputs (1: in this process, e.g. under a profiler)")
     ap.add_argument("--inputs", default=None,
                     help="file of drawn inputs: loaded when it exists, else written after drawing")
-    ap.add_argument("--extras-only", default="workloads,differentiation,modes",
-                    help="comma list of side measurements to run (workloads, differentiation, modes)")
+    ap.add_argument("--extras-only", default="workloads,differentiation,modes,paper_shape",
+                    help="comma list of side measurements to run (workloads, differentiation, modes, "
+                         "paper_shape)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the sampler has no multi-GPU path (ligands and "
@@ -525,6 +557,9 @@ def main():
             print("other workloads done", file=sys.stderr, flush=True)
         if "differentiation" in which:
             ex["differentiation"] = differentiation_rate(D)
+        if "paper_shape" in which:
+            ex["paper_shape"] = paper_shape_rate(D)
+            print("paper-shaped dockings done", file=sys.stderr, flush=True)
         if "modes" in which:
             ex.update(extras(D, pks[0], L, T, S))
         out["extras"] = ex
