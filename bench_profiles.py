@@ -14,7 +14,9 @@ MI355X) and writes, under profiles/:
   size in the same run.  traffic.json carries a SHA-256 of the library
   sources; bench.py uses it only while the sources hash the same.
 
-    python bench_profiles.py [--out profiles] [--runs gpurun_out]
+    python bench_profiles.py --runs OUT [--out profiles]
+
+OUT is the folder the runs wrote to (`<out>` in the commands).
 """
 import argparse
 import csv
@@ -31,9 +33,9 @@ N_BUCKET_LAUNCHES = 6        # MC-step launches of the mixed-pocket step (one pe
 
 CMD_INPUTS = ("python bench.py --inputs /tmp/c5.pkl --steps 1 --warmup 0 --no-plain --no-cpu-baseline "
               "--no-extras")
-CMD_TRACE = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d <repo>/gpurun_out/prof_trace "
+CMD_TRACE = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d <out>/prof_trace "
              "-o trace -- python3 <repo>/bench.py --inputs /tmp/c5.pkl --workers 1 --steps 1 --warmup 0 "
-             "--no-plain --no-cpu-baseline --extras-only differentiation --out <repo>/gpurun_out/prof_trace_bench.json")
+             "--no-plain --no-cpu-baseline --extras-only differentiation --out <out>/prof_trace_bench.json")
 PMC_A = ("FETCH_SIZE SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_LDS SQ_INSTS_SALU "
          "SQ_INSTS_VMEM_RD SQ_WAVES")
 PMC_B = ("WRITE_SIZE TCC_HIT_sum TCC_REQ_sum SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_LDS SQ_LDS_IDX_ACTIVE "
@@ -41,7 +43,7 @@ PMC_B = ("WRITE_SIZE TCC_HIT_sum TCC_REQ_sum SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST
 
 
 def cmd_pmc(counters, d):
-    return ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc %s --output-format csv -d <repo>/gpurun_out/%s -o pmc "
+    return ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc %s --output-format csv -d <out>/%s -o pmc "
             "-- python3 <repo>/bench.py --inputs /tmp/c5.pkl --workers 1 --steps 1 --warmup 0 --no-plain "
             "--no-cpu-baseline --no-extras --calib-copy-mib 256" % (counters, d))
 
@@ -70,7 +72,7 @@ def trace_summaries(runs, out):
         s[0] += 1
         s[1] += dur / 1e6
     lines = ["# Kernel trace: the mixed-pocket workload (one step) and the differentiation workload", "",
-             "Commands (repo root = <repo>; the first, unprofiled, draws the inputs and saves them; "
+             "Commands (repo root = <repo>, run outputs in <out>; the first, unprofiled, draws the inputs and saves them; "
              "`python bench_profiles.py` wrote this file):", "",
              "    " + CMD_INPUTS, "    " + CMD_TRACE, "",
              "One step: 16 map rebuilds, the batched sampler over 65,536 ligands (64 trajectories x 200 MC steps x",
@@ -213,7 +215,7 @@ def counter_summaries(runs, out):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--runs", default=os.path.join(ROOT, "gpurun_out"), help="folder holding the runs' outputs")
+    ap.add_argument("--runs", required=True, help="folder holding the runs' outputs (<out> in the commands)")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     args = ap.parse_args()
     tr, ev = trace_summaries(args.runs, args.out)
