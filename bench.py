@@ -248,6 +248,19 @@ def _form_ms(D, pockets, H, T, S, form):
     return 1e3 * (time.perf_counter() - t0)
 
 
+def _docking_buffers_bytes(pocket, L, T, top_n=8):
+    """Device bytes one docking of the largest ligand of L holds, counted
+    from the buffer sizes (a device-memory delta is blurred by the
+    allocators' caching): the combined maps (8 types x nodes x 4 B), the
+    run's state (current and best q and E, evaluation counts: T x
+    (2 q_stride + 3) x 4 B; q_stride = 6 + max torsions of L) and the best-
+    pose outputs (top_n x (E, E_screen, index, q, xyz))."""
+    nodes = int(np.prod(pocket.dims))
+    n_max = int(np.max(np.diff(L.atom_off)))
+    qs = 6 + max(int(np.sum(L.rotatable[L.bond_off[i]:L.bond_off[i + 1]])) for i in range(L.n_ligands))
+    return 8 * nodes * 4 + T * (2 * qs + 3) * 4 + top_n * (3 + qs + 3 * n_max) * 4
+
+
 def paper_shape_rate(D, n_single=8):
     """Dockings in the paper's sampling shape (1,024 copies x 8 MC steps x
     10 Adam steps per ligand; Methods, "Conformation sampling") on the
@@ -257,23 +270,9 @@ def paper_shape_rate(D, n_single=8):
     wall time.  Context for the paper's per-docking times (Table 5), which
     were taken on other hardware with a pipeline that includes more than
     this path."""
-    import torch
     pks, L, wl = synth.workload("C2")
     T, S = 1024, 8
-    # device memory of one docking: pocket maps, one ligand, the run's
-    # state and the best-pose outputs, all alive at once
-    torch.cuda.synchronize()
-    free0 = torch.cuda.mem_get_info()[0]
     pockets = load_pockets(D, pks, False)
-    L0 = L.subset(np.array([0]))
-    H0 = D.dock_load_ligands(L0.atom_off, L0.element, L0.n_h, L0.xyz, L0.bond_off, L0.bonds, L0.rotatable,
-                             pocket_index=L0.pocket_index)
-    run0 = D.dock_sample(pockets, H0, n_traj=T, n_steps=S, n_local=N_LOCAL, seed=0, form=D.FORM_BATCHED)
-    st0 = D.dock_run_state(run0)
-    best0 = D.dock_best_poses(H0, T, st0["E_best"], st0["q_best"], top_n=8, want_xyz=True)
-    torch.cuda.synchronize()
-    single_mb = (free0 - torch.cuda.mem_get_info()[0]) / 2**20
-    del run0, st0, best0, H0
     H = D.dock_load_ligands(L.atom_off, L.element, L.n_h, L.xyz, L.bond_off, L.bonds, L.rotatable,
                             pocket_index=L.pocket_index)
     order = np.argsort(np.diff(L.atom_off), kind="stable")
@@ -288,7 +287,7 @@ def paper_shape_rate(D, n_single=8):
     ev = T * (1 + S * (N_LOCAL + 1))
     return dict(n_traj=T, n_steps=S, n_local=N_LOCAL, evals_per_docking=ev,
                 single_ms_per_docking=round(float(np.mean(single)), 3), single_ligands=int(len(pick)),
-                single_device_mb=round(single_mb, 1),
+                single_buffers_mb=round(_docking_buffers_bytes(pockets[0], L, T) / 2**20, 2),
                 batch_ligands=H.n, batch_ms=round(batch, 2), batch_ms_per_pair=round(batch / H.n, 4),
                 batch_evals_per_s=round(ev * H.n / (batch * 1e-3), 1),
                 paper_context="Table 5 (RTX A6000, whole pipeline): 2.3 s per docking single, 0.33 s per pair batch")
