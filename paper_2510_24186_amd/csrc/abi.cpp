@@ -1809,8 +1809,8 @@ int dock_run_restart(dock_run_t r, uint32_t seed, void* stream) try {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t nt = size_t(r->n_lig) * r->T;
   // counters and the trace back to their initial values with fill kernels
-  // (the call only enqueues kernels: it allocates nothing and can be
-  // captured into a graph)
+  // rather than memsets (the call enqueues kernels only and allocates
+  // nothing)
   HIP_TRY(launch_fill_int(r->n_evals, int(nt), 0, s));
   HIP_TRY(launch_fill_int(r->d_step, 1, 0, s));
   HIP_TRY(launch_fill_int(r->d_step + 1, 1, int(seed), s));

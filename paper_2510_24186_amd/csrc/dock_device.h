@@ -147,8 +147,8 @@ DK_INLINE float group_scan(float v) {
 // Pass layout: each slot takes two entries, the pair word and radius sum,
 // then the E_clash constants d_clash^2 (negated for a donor/acceptor pair)
 // and log2(d_clash) (FP32 bit patterns in a second PairRec), so record p
-// still starts at entry 2p; after the n_prec slots come the pull words, one
-// 8-byte entry per atom and pass (see PassPlan).  An empty slot names atoms 0
+// still starts at entry 2p; after the n_prec slots come the pull bytes,
+// apl * cap per lane and pass (see PassPlan).  An empty slot names atoms 0
 // and 0 with a radius sum of -1e4 and zero clash constants, which makes every
 // term of both presets exactly zero.
 constexpr uint32_t kPairEmpty = 0x80u << 24;

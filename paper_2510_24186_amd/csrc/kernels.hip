@@ -699,8 +699,9 @@ DK_INLINE void run_traj(const SampleArgs& a, const LaneLig<APL>& L, const Pocket
   }
 }
 
-// Three waves per SIMD: the register budget (168) that the step loop fits
-// without spilling.
+// Three waves per SIMD (168 VGPRs).  With two atoms per lane the step loop
+// needs more and spills a few registers to scratch (served from L2, outside
+// the pair-pass loop); two waves per SIMD without spills measured slower.
 template <int LPP, int APL, int BLOCK, int MODE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) sample_kernel(SampleArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
