@@ -484,6 +484,16 @@ def main():
     print("timed %d steps in %.3fs" % (args.steps, t1 - t0), file=sys.stderr, flush=True)
     ms_step = 1e3 * (t1 - t0) / args.steps
     plan = D.dock_run_plan(step.run)
+    if args.graph:
+        # graph replays record no per-launch events: the roofline's launch
+        # durations come from one more step of the same plan, launched eagerly
+        keep = None
+        eager = Step(D, pks, H, T, S, adjoint, 0)
+        eager(2000)
+        torch.cuda.synchronize()
+        launch_stats = [D.dock_run_launch_stats(eager.run)]
+        del eager
+        print("eager step for the launch durations done", file=sys.stderr, flush=True)
 
     # roofline of the sampler kernel: algorithmic FP32 work of the MC-step
     # launches / their event-measured durations, per lane configuration
@@ -514,6 +524,7 @@ def main():
                     traffic=None if rec is None else round(rec["hbm_bytes"]),
                     frac_of_nonpacked_peak=round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
                     kernel="sample_kernel<%d,%d,%d>" % (dom["lanes"], dom["apl"], dom["block"]),
+                    launch_timing="eager step after the graph-replayed ones" if args.graph else "timed steps",
                     launch_ms=round(launch_ms, 3),
                     flop_per_launch=dom["flop"],
                     gather_bytes_per_launch=dom["atom_evals"] * 32.0,
