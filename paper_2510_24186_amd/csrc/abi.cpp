@@ -1151,13 +1151,18 @@ struct dock_run_s {
   std::vector<hipEvent_t> event_pool;
   size_t events_used = 0;
   bool recording = false;
-  // batched form with several buckets: bucket b > 0 runs on side[b - 1],
-  // forked from and joined back into the caller's stream, so a bucket too
-  // small to fill the chip and the tail of a large one overlap.  The side
-  // streams belong to the device's process-wide pool (side_streams).
+  // batched form: the buckets run in groups, one per occupancy class (blocks
+  // per CU), highest first.  The buckets of a group run concurrently: the
+  // first on the caller's stream, the k-th on side[k - 1], forked from and
+  // joined back into the caller's stream, so a bucket too small to fill the
+  // chip and the tail of a large one overlap.  A group starts when the one
+  // before it has ended: blocks of kernels of different occupancy classes
+  // sharing a CU lower the waves it holds.  The side streams belong to the
+  // device's process-wide pool (side_streams).
+  std::vector<std::vector<int>> occ_groups;
   std::vector<hipStream_t> side;
-  std::vector<hipEvent_t> join;
-  hipEvent_t fork = nullptr;
+  std::vector<std::vector<hipEvent_t>> join;  // [group][side stream]
+  std::vector<hipEvent_t> fork;               // [group]
 };
 
 // Side streams of the batched form, shared by every run on a device and kept
@@ -1230,8 +1235,10 @@ static void free_run(dock_run_s* r) {
     r->L->n_runs.fetch_sub(1);
   }
   for (hipEvent_t e : r->event_pool) (void)hipEventDestroy(e);
-  for (hipEvent_t e : r->join) (void)hipEventDestroy(e);
-  if (r->fork) (void)hipEventDestroy(r->fork);
+  for (const auto& jg : r->join)
+    for (hipEvent_t e : jg) (void)hipEventDestroy(e);
+  for (hipEvent_t e : r->fork)
+    if (e) (void)hipEventDestroy(e);
   if (r->gexec) (void)hipGraphExecDestroy(r->gexec);
   if (r->graph) (void)hipGraphDestroy(r->graph);
   if (r->ev0) (void)hipEventDestroy(r->ev0);
@@ -1283,38 +1290,52 @@ static hipError_t enqueue_phase(dock_run_s* r, bool init, int steps, hipStream_t
                                                           : r->p.steps_per_launch;
   const int n_chunks = init ? 1 : (steps + chunk - 1) / chunk;
   hipError_t e = hipSuccess;
-  const bool fork = r->p.form == DOCK_FORM_BATCHED && !r->side.empty();
   const int nb = int(r->buckets.size()), np = r->n_part;
+  auto chunk_args = [&](int c) {
+    SampleArgs a = base_args(r);
+    a.init = init ? 1 : 0;
+    a.step_off = init ? 0 : c * chunk;
+    a.step_count = init ? 0 : std::min(chunk, steps - c * chunk);
+    return a;
+  };
   if (r->p.form == DOCK_FORM_BATCHED) {
     const int need = n_chunks * nb * np;
     if (need > r->n_queue) return hipErrorInvalidValue;
     e = launch_fill_int(r->d_queue, need, 0, s);
     if (e != hipSuccess) return e;
-  }
-  if (fork) {
-    if ((e = hipEventRecord(r->fork, s)) != hipSuccess) return e;
-    for (hipStream_t q : r->side)
-      if ((e = hipStreamWaitEvent(q, r->fork, 0)) != hipSuccess) return e;
-  }
-  for (int c = 0; c < n_chunks; ++c) {
-    SampleArgs a = base_args(r);
-    a.init = init ? 1 : 0;
-    a.step_off = init ? 0 : c * chunk;
-    a.step_count = init ? 0 : std::min(chunk, steps - c * chunk);
-    if (r->p.form == DOCK_FORM_BATCHED) {
-      for (size_t b = 0; b < r->buckets.size(); ++b) {
-        const Bucket& B = r->buckets[b];
-        a.items = r->d_items + B.item_off;
-        a.n_items = B.n_items;
-        a.queue = r->d_queue + (c * nb + int(b)) * np;
-        a.part_off = r->d_part + B.part_base;
-        a.n_part = np;
-        a.max_pairs = B.max_pairs;
-        const hipStream_t bs = (fork && b > 0) ? r->side[b - 1] : s;
-        e = timed_launch(r, a, int(b), B.lpp, B.apl, B.grid, B.block, bs);
-        if (e != hipSuccess) return e;
+    // occupancy classes one after the other; within one, the buckets run
+    // concurrently, each through all of its chunks on its own stream
+    for (size_t gi = 0; gi < r->occ_groups.size(); ++gi) {
+      const std::vector<int>& P = r->occ_groups[gi];
+      if (P.size() > 1) {
+        if ((e = hipEventRecord(r->fork[gi], s)) != hipSuccess) return e;
+        for (size_t k = 1; k < P.size(); ++k)
+          if ((e = hipStreamWaitEvent(r->side[k - 1], r->fork[gi], 0)) != hipSuccess) return e;
       }
-    } else {
+      for (int c = 0; c < n_chunks; ++c) {
+        SampleArgs a = chunk_args(c);
+        for (size_t k = 0; k < P.size(); ++k) {
+          const int b = P[k];
+          const Bucket& B = r->buckets[b];
+          a.items = r->d_items + B.item_off;
+          a.n_items = B.n_items;
+          a.queue = r->d_queue + (c * nb + b) * np;
+          a.part_off = r->d_part + B.part_base;
+          a.n_part = np;
+          a.max_pairs = B.max_pairs;
+          e = timed_launch(r, a, b, B.lpp, B.apl, B.grid, B.block, k == 0 ? s : r->side[k - 1]);
+          if (e != hipSuccess) return e;
+        }
+      }
+      if (P.size() > 1)
+        for (size_t k = 1; k < P.size(); ++k) {
+          if ((e = hipEventRecord(r->join[gi][k - 1], r->side[k - 1])) != hipSuccess) return e;
+          if ((e = hipStreamWaitEvent(s, r->join[gi][k - 1], 0)) != hipSuccess) return e;
+        }
+    }
+  } else {
+    for (int c = 0; c < n_chunks; ++c) {
+      SampleArgs a = chunk_args(c);
       for (int l = 0; l < r->n_lig; ++l) {
         const Bucket& B = r->buckets[r->lig_bucket[l]];
         a.items = r->d_items + r->lig_item_off[l];
@@ -1328,11 +1349,6 @@ static hipError_t enqueue_phase(dock_run_s* r, bool init, int steps, hipStream_t
       }
     }
   }
-  if (fork)
-    for (size_t k = 0; k < r->side.size(); ++k) {
-      if ((e = hipEventRecord(r->join[k], r->side[k])) != hipSuccess) return e;
-      if ((e = hipStreamWaitEvent(s, r->join[k], 0)) != hipSuccess) return e;
-    }
   if (!init) e = launch_add_int(r->d_step, steps, s);
   return e;
 }
@@ -1590,21 +1606,40 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
       if (lds > 64 * 1024) return bail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
       const int per_cu = sample_max_blocks_per_cu(B.lpp, B.apl, B.block, r->mode, lds);
       B.grid = std::min(B.n_items, per_cu * n_cu);
+      B.per_cu = per_cu;
+    }
+    // launch groups: one per occupancy class, highest first
+    std::vector<int> order(r->buckets.size());
+    for (size_t b = 0; b < order.size(); ++b) order[b] = int(b);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return r->buckets[x].per_cu > r->buckets[y].per_cu; });
+    for (const int b : order) {
+      if (r->occ_groups.empty() || r->buckets[r->occ_groups.back()[0]].per_cu != r->buckets[b].per_cu)
+        r->occ_groups.emplace_back();
+      r->occ_groups.back().push_back(b);
     }
   }
   for (const Bucket& B : r->buckets)
     if (sample_lds_bytes(B.lpp, B.apl, B.block, B.max_pairs) > 64 * 1024)
       return bail(DOCK_E_LIMIT, "pair list too long for the LDS budget");
-  if (p->form == DOCK_FORM_BATCHED && r->buckets.size() > 1) {
-    if (side_streams(r->buckets.size() - 1, &r->side) != DOCK_OK) {
+  size_t widest = 0;
+  for (const auto& P : r->occ_groups) widest = std::max(widest, P.size());
+  if (p->form == DOCK_FORM_BATCHED && widest > 1) {
+    if (side_streams(widest - 1, &r->side) != DOCK_OK) {
       const std::string m = g_err;
       return bail(DOCK_E_HIP, m);
     }
-    hipError_t se = hipEventCreateWithFlags(&r->fork, hipEventDisableTiming);
-    for (size_t b = 1; b < r->buckets.size() && se == hipSuccess; ++b) {
-      hipEvent_t j = nullptr;
-      se = hipEventCreateWithFlags(&j, hipEventDisableTiming);
-      if (se == hipSuccess) r->join.push_back(j);
+    hipError_t se = hipSuccess;
+    r->fork.assign(r->occ_groups.size(), nullptr);
+    r->join.resize(r->occ_groups.size());
+    for (size_t gi = 0; gi < r->occ_groups.size() && se == hipSuccess; ++gi) {
+      if (r->occ_groups[gi].size() < 2) continue;
+      se = hipEventCreateWithFlags(&r->fork[gi], hipEventDisableTiming);
+      for (size_t k = 1; k < r->occ_groups[gi].size() && se == hipSuccess; ++k) {
+        hipEvent_t j = nullptr;
+        se = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+        if (se == hipSuccess) r->join[gi].push_back(j);
+      }
     }
     if (se != hipSuccess) return bail(DOCK_E_HIP, std::string("bucket events: ") + hipGetErrorString(se));
   }
