@@ -76,7 +76,8 @@ def trace_summaries(runs, out):
              "`python bench_profiles.py` wrote this file):", "",
              "    " + CMD_INPUTS, "    " + CMD_TRACE, "",
              "One step: 16 map rebuilds, the batched sampler over 65,536 ligands (64 trajectories x 200 MC steps x",
-             "10 Adam steps, 9.23 G evaluations) as six lane-bucket launches on concurrent streams, best poses, and",
+             "10 Adam steps, 9.23 G evaluations) as six lane-bucket launches on concurrent streams, grouped by",
+             "occupancy class, best poses, and",
              "the deterministic adjoint of the summed best-pose energies to every pocket's maps and weights; then",
              "the differentiation workload (2,048 poses, Vina-form terms) forward and adjoint, twice.", "",
              "## Kernel statistics (from the run's kernel dispatch records; durations in ms)", "",
@@ -94,8 +95,8 @@ def trace_summaries(runs, out):
     grid_threads = [b["grid"] for b in dom["buckets"] if abs(b["ms"] - dom["launch_ms"]) < 1e-3][0] * 256
     dom_trace = [d for n, g, wg, d, lds, scr, st in rows if key in short(n) and g == grid_threads][-1] / 1e6
     lines += ["", "The first six dispatches draw and score the initial poses; the next six are the MC-step "
-              "launches of", "the six buckets, overlapped on concurrent streams.  The dominant launch (most "
-              "algorithmic work) is", "`%s, 0>` with grid %d threads: %.3f ms here;" % (key, grid_threads, dom_trace),
+              "launches of", "the six buckets, concurrent within each occupancy class (three blocks per CU, "
+              "then two).  The dominant", "launch (most algorithmic work) is", "`%s, 0>` with grid %d threads: %.3f ms here;" % (key, grid_threads, dom_trace),
               "bench.py measured the same launch with HIP events on its stream as %.3f ms (`roofline.launch_ms`)."
               % dom["launch_ms"], "",
               "Same run, bench line: value %.1f M evals/s, dominant launch %.3f TFLOP/s = %.4f of 157.3." % (
