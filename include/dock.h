@@ -292,10 +292,13 @@ void dock_sample_params_default(dock_sample_params* p);
 
 /* Creates a run, draws the initial poses, scores them and advances every
  * trajectory by p->n_steps MC steps.  The run owns its state buffers.
- * In the batched form the lane buckets after the first run on side streams
- * forked from `stream` and joined back into it; the library keeps a pool of
- * them per device for the life of the process, shared by all runs (capturing
- * runs as graphs from several host threads at once is not supported).
+ * In the batched form the lane buckets run in groups, one per occupancy
+ * class (blocks per CU), highest first, each group after the previous one;
+ * within a group the first bucket runs on `stream` and the others on side
+ * streams forked from `stream` and joined back into it.  The library keeps
+ * a pool of side streams per device for the life of the process, shared by
+ * all runs (capturing runs as graphs from several host threads at once is
+ * not supported).
  * A run's ligands of 33-64 atoms are laid out two atoms per lane when its
  * trajectories of such ligands fill at least two waves per wave slot of the
  * device (two poses per wavefront), else one atom per lane. */
