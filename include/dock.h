@@ -18,8 +18,10 @@
  *    are HIP device memory owned by the caller (e.g. torch tensor storage).
  *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
  *    enqueued asynchronously on it unless stated otherwise.
- *  - Handles are immutable after creation (runs excepted), so concurrent
- *    read-only calls on different streams are safe.
+ *  - Handles are immutable after creation (runs excepted): calls that only
+ *    read them do not race on them.  Use of the library from several host
+ *    threads at once has not been verified, and the sampler does not
+ *    support it (dock_sample).
  *  - Poses: q = (Tx, Ty, Tz, alpha, beta, gamma, theta_0 .. theta_{n_t-1}),
  *    row-major with a caller-chosen row stride q_stride >= 6 + n_t.  T is
  *    where the root fragment's centroid lands; R = Rz(alpha) Ry(beta)
@@ -297,8 +299,10 @@ void dock_sample_params_default(dock_sample_params* p);
  * within a group the first bucket runs on `stream` and the others on side
  * streams forked from `stream` and joined back into it.  The library keeps
  * a pool of side streams per device for the life of the process, shared by
- * all runs (capturing runs as graphs from several host threads at once is
- * not supported).
+ * all runs.  Runs are created, advanced, restarted and freed from one host
+ * thread at a time: with use_graph = 1 (the default) the first MC-step
+ * phase of a run is captured as a graph through the shared side streams,
+ * and runs used from several threads at once are not supported.
  * A run's ligands of 33-64 atoms are laid out two atoms per lane when its
  * trajectories of such ligands fill at least two waves per wave slot of the
  * device (two poses per wavefront), else one atom per lane. */
