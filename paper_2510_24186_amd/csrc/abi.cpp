@@ -7,12 +7,14 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -228,6 +230,23 @@ static std::string device_arch() {
   std::string name = hipGetDeviceProperties(&prop, dev) == hipSuccess ? std::string(prop.gcnArchName) : "unknown";
   names[dev] = name;
   return name;
+}
+
+// Runs f(i) for i in [0, n) on up to OMP_NUM_THREADS (else the hardware's)
+// host threads, at most 64.  f must not throw.
+template <class F>
+static void parallel_for(int n, F&& f) {
+  int nt = int(std::thread::hardware_concurrency());
+  if (const char* v = std::getenv("OMP_NUM_THREADS")) nt = std::atoi(v);
+  nt = std::max(1, std::min({nt, 64, (n + 63) / 64}));
+  std::atomic<int> next(0);
+  auto work = [&] {
+    for (int i; (i = next.fetch_add(1)) < n;) f(i);
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (std::thread& t : pool) t.join();
 }
 
 extern "C" {
@@ -493,6 +512,204 @@ static int bit_length(int v) {
   return b;
 }
 
+// Device records of one prepared ligand, with offsets into its own arrays
+// (the merge in dock_load_ligands shifts them into the packed arrays).
+struct PackedLigand {
+  LigDev g;
+  std::vector<float4> atoms;
+  std::vector<FragDev> frags;
+  std::vector<TorsDev> tors;
+  std::vector<PairRec> pairs;
+};
+
+static void pack_ligand(const LigandHost& H, const TypePair* tab, PackedLigand& P) {
+  std::vector<float4>& atoms = P.atoms;
+  std::vector<FragDev>& frags = P.frags;
+  std::vector<TorsDev>& tors = P.tors;
+  std::vector<PairRec>& pairs = P.pairs;
+  LigDev& g = P.g;
+  std::memset(&g, 0, sizeof g);
+  g.n_atoms = H.n_atoms;
+  g.n_tors = H.n_tors;
+  g.n_frags = H.n_frags;
+  g.n_pairs = int(H.pair_i.size());
+  g.atom_off = int(atoms.size());
+  g.pair_off = int(pairs.size());
+  g.frag_off = int(frags.size());
+  g.tors_off = int(tors.size());
+  g.pocket = H.pocket;
+  g.n_dof = 6 + H.n_tors;
+  g.fk_rounds = bit_length(H.height);
+  for (int c = 0; c < 3; ++c) {
+    g.c0[c] = float(H.c0[c]);
+    g.box_min[c] = H.box_min[c];
+    g.box_max[c] = H.box_max[c];
+  }
+  // coordinates relative to the root centroid c0 (FP64 difference, rounded
+  // once): the rotation then acts on vectors of ligand size, not on
+  // absolute positions, which keeps FP32 forward kinematics accurate
+  for (int na = 0; na < H.n_atoms; ++na) {
+    const int a = H.dfs_atom[na];
+    const int bits = int(H.type[a]) | (H.frag_new[H.atom_frag[a]] << 8) | (a << 16);
+    float4 v = make_float4(float(double(H.x0[3 * a]) - H.c0[0]), float(double(H.x0[3 * a + 1]) - H.c0[1]),
+                           float(double(H.x0[3 * a + 2]) - H.c0[2]), 0.f);
+    std::memcpy(&v.w, &bits, 4);
+    atoms.push_back(v);
+  }
+  std::vector<int> frag_tors(H.n_frags, -1);
+  for (int k = 0; k < H.n_tors; ++k) frag_tors[H.tors_frag[k]] = k;
+  for (int nf = 0; nf < H.n_frags; ++nf) {
+    const int f = H.dfs_frag[nf];
+    FragDev fd{};
+    if (H.frag_parent[f] < 0) {
+      fd.parent = -1;
+      fd.dof = -1;
+    } else {
+      const int k = frag_tors[f];
+      const int a = H.tors_a[k], b = H.tors_b[k];
+      double u[3], n2 = 0;
+      for (int c = 0; c < 3; ++c) {
+        u[c] = double(H.x0[3 * b + c]) - double(H.x0[3 * a + c]);
+        n2 += u[c] * u[c];
+      }
+      const double inv = 1.0 / std::sqrt(n2);
+      for (int c = 0; c < 3; ++c) {
+        fd.u[c] = float(u[c] * inv);
+        fd.xb[c] = float(double(H.x0[3 * b + c]) - H.c0[c]);
+      }
+      fd.parent = H.frag_new[H.frag_parent[f]];
+      fd.dof = 6 + k;
+    }
+    frags.push_back(fd);
+  }
+  // torsion k moves the DFS subtree of its child fragment: a contiguous range
+  std::vector<int> first(H.n_frags, 0), last(H.n_frags, 0);  // atom range per new frag id
+  {
+    std::vector<int> start(H.n_frags, -1), stop(H.n_frags, -1);
+    for (int na = 0; na < H.n_atoms; ++na) {
+      const int nf = H.frag_new[H.atom_frag[H.dfs_atom[na]]];
+      if (start[nf] < 0) start[nf] = na;
+      stop[nf] = na + 1;
+    }
+    // subtree end = max stop over the DFS subtree; in pre-order the subtree
+    // of nf is nf .. nf + size - 1
+    std::vector<int> size(H.n_frags, 1);
+    for (int nf = H.n_frags - 1; nf >= 1; --nf) {
+      const int par = frags[g.frag_off + nf].parent;
+      size[par] += size[nf];
+    }
+    for (int nf = 0; nf < H.n_frags; ++nf) {
+      first[nf] = start[nf];
+      last[nf] = stop[nf + size[nf] - 1];
+    }
+  }
+  for (int k = 0; k < H.n_tors; ++k) {
+    const int nf = H.frag_new[H.tors_frag[k]];
+    TorsDev t{};
+    t.sub_begin = first[nf];
+    t.sub_end = last[nf];
+    t.a = H.atom_new[H.tors_a[k]];
+    t.b = H.atom_new[H.tors_b[k]];
+    tors.push_back(t);
+  }
+  // device pair records: with one atom per lane, passes of one group's
+  // width whose forces are gathered per atom (no LDS atomics); with two
+  // atoms per lane, the caller's order, strided over the lanes
+  std::vector<int> pi_new(H.pair_i.size()), pj_new(H.pair_j.size());
+  for (size_t p = 0; p < H.pair_i.size(); ++p) {
+    pi_new[p] = H.atom_new[H.pair_i[p]];
+    pj_new[p] = H.atom_new[H.pair_j[p]];
+  }
+  auto record = [&](int i0, int j0) {
+    PairRec pr{};
+    if (i0 < 0) {
+      pr.w = kPairEmpty;
+      pr.rsum = kEmptyRsum;
+      return pr;
+    }
+    const int ti = H.type[H.dfs_atom[i0]], tj = H.type[H.dfs_atom[j0]];
+    const TypePair& tp = tab[ti * kTypes + tj];
+    pr.w = uint32_t(i0) | (uint32_t(j0) << 8) | (uint32_t(ti) << 16) | (uint32_t(tj) << 20) |
+           (tp.flags << 24);
+    pr.rsum = tp.rsum;
+    return pr;
+  };
+  auto bits = [](float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return u;
+  };
+  // one pair layout for a lane configuration, appended to `pairs`
+  auto emit_layout = [&](const LaneCfg& lc) {
+    PairLayout lay{};
+    lay.pair_off = int(pairs.size());
+    PassPlan plan;
+    if (!pi_new.empty()) plan = schedule_passes(H.n_atoms, pi_new, pj_new, lc.lpp, lc.apl);
+    // the pass layout stages 2 entries per slot and apl * cap pull bytes
+    // per lane and pass; with two atoms per lane above 64 atoms it is kept
+    // only where it fits the LDS budget
+    const size_t pull_bytes = size_t(plan.n_pass) * lc.lpp * lc.apl * plan.cap;
+    const size_t pass_entries = plan.slot_i.size() * 2 + pull_bytes / sizeof(PairRec) + 1;
+    if (plan.n_pass > 0 &&
+        (H.n_atoms <= 64 || pass_entries * sizeof(PairRec) <= kPassStageBytes)) {
+      lay.n_pass = plan.n_pass;
+      lay.pass_w = lc.lpp;
+      lay.pass_apl = lc.apl;
+      lay.pull_cap = plan.cap;
+      // 16-byte slot records (pair word, radius sum, d_clash^2 as the
+      // device squares it, log2 d_clash), then the pull bytes
+      for (size_t s = 0; s < plan.slot_i.size(); ++s) {
+        const int i0 = plan.slot_i[s], j0 = plan.slot_j[s];
+        pairs.push_back(record(i0, j0));
+        PairRec cl{};
+        if (i0 >= 0) {
+          const TypePair& tp = tab[H.type[H.dfs_atom[i0]] * kTypes + H.type[H.dfs_atom[j0]]];
+          // negated for a donor/acceptor pair: the kernel tests
+          // |d_clash^2| for the clash term and the sign for the
+          // hydrogen-bond term
+          cl.w = bits((tp.flags & 1u) ? -tp.dclash2 : tp.dclash2);
+          cl.rsum = float(std::log2(double(tp.dclash)));
+        }
+        pairs.push_back(cl);
+      }
+      // pull bytes per (pass, lane): the lane's atoms one after the other,
+      // the first `cap` bytes of each atom's pull list
+      std::vector<uint8_t> pb(pull_bytes);
+      const int per_lane = lc.apl * plan.cap;
+      for (int ps = 0; ps < plan.n_pass; ++ps)
+        for (int ln = 0; ln < lc.lpp; ++ln)
+          for (int sa = 0; sa < lc.apl; ++sa) {
+            const uint64_t w = plan.pulls[size_t(ps) * plan.n_pull + lc.apl * ln + sa];
+            for (int b = 0; b < plan.cap; ++b)
+              pb[(size_t(ps) * lc.lpp + ln) * per_lane + sa * plan.cap + b] = uint8_t(w >> (8 * b));
+          }
+      for (size_t o = 0; o < pb.size(); o += sizeof(PairRec)) {
+        PairRec pw;
+        std::memcpy(&pw, pb.data() + o, sizeof(PairRec));
+        pairs.push_back(pw);
+      }
+      // padding: the kernel reads each 4-byte pull word with its successor
+      pairs.push_back(PairRec{});
+      lay.n_prec = int(plan.slot_i.size());
+    } else {
+      for (size_t p = 0; p < pi_new.size(); ++p) pairs.push_back(record(pi_new[p], pj_new[p]));
+      lay.n_prec = int(pi_new.size());
+    }
+    lay.n_stage = int(pairs.size()) - lay.pair_off;
+    return lay;
+  };
+  const LaneCfg lc = lane_cfg(g, 0), la = lane_cfg(g, 0, true);
+  const PairLayout prim = emit_layout(lc);
+  g.pair_off = prim.pair_off;
+  g.n_prec = prim.n_prec;
+  g.n_pass = prim.n_pass;
+  g.pass_w = prim.pass_w;
+  g.pull_cap = prim.pull_cap;
+  g.pass_apl = prim.pass_apl;
+  g.alt = (la.lpp == lc.lpp && la.apl == lc.apl) ? prim : emit_layout(la);
+  g.n_stage = prim.n_stage;
+}
+
 int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* out) try {
   (void)stream;
   if (!d || !out) return fail(DOCK_E_ARG, "null argument");
@@ -510,17 +727,32 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
   L->n = d->n_ligands;
   L->host_only = d->host_only != 0;
   L->host.resize(L->n);
-  std::string err;
-  for (int i = 0; i < L->n; ++i) {
+  // typing, fragments, torsion tree and pair list of every ligand, in
+  // parallel; the first failing ligand (in order) is reported
+  std::vector<int> prep_rc(L->n, DOCK_OK);
+  std::vector<std::string> prep_err(L->n);
+  parallel_for(L->n, [&](int i) {
     const int a0 = d->atom_off[i], b0 = d->bond_off[i];
     const int n = d->atom_off[i + 1] - a0, nb = d->bond_off[i + 1] - b0;
-    int rc = prepare_ligand(n, d->element + a0, d->n_h + a0, d->xyz + 3 * size_t(a0), nb,
-                            nb ? d->bonds + 2 * size_t(b0) : nullptr, nb ? d->rotatable + b0 : nullptr,
-                            d->box_min ? d->box_min + 3 * size_t(i) : nullptr,
-                            d->box_max ? d->box_max + 3 * size_t(i) : nullptr, L->host[i], err);
-    if (rc != DOCK_OK) {
+    try {
+      prep_rc[i] = prepare_ligand(n, d->element + a0, d->n_h + a0, d->xyz + 3 * size_t(a0), nb,
+                                  nb ? d->bonds + 2 * size_t(b0) : nullptr, nb ? d->rotatable + b0 : nullptr,
+                                  d->box_min ? d->box_min + 3 * size_t(i) : nullptr,
+                                  d->box_max ? d->box_max + 3 * size_t(i) : nullptr, L->host[i], prep_err[i]);
+    } catch (const std::bad_alloc&) {
+      prep_rc[i] = DOCK_E_OOM;
+      prep_err[i] = "host allocation failed";
+    } catch (...) {
+      prep_rc[i] = DOCK_E_ARG;
+      prep_err[i] = "preparation failed";
+    }
+  });
+  for (int i = 0; i < L->n; ++i) {
+    if (prep_rc[i] != DOCK_OK) {
+      const int rc = prep_rc[i];
+      const std::string msg = "ligand " + std::to_string(i) + ": " + prep_err[i];
       delete L;
-      return fail(rc, "ligand " + std::to_string(i) + ": " + err);
+      return fail(rc, msg);
     }
     L->host[i].pocket = d->pocket_index ? d->pocket_index[i] : 0;
     if (L->host[i].pocket < 0) {
@@ -528,197 +760,47 @@ int dock_load_ligands(const dock_ligand_desc* d, void* stream, dock_ligands_t* o
       return fail(DOCK_E_ARG, "negative pocket index");
     }
   }
-  // pack (DFS atom order)
+  // pack (DFS atom order): each ligand's records on its own, in parallel,
+  // then concatenated in ligand order with the offsets shifted
+  TypePair tab[kTypes * kTypes];
+  type_pair_table(DOCK_PRESET_TRIDS, tab);
+  std::vector<PackedLigand> packed(L->n);
+  std::vector<int> pack_rc(L->n, DOCK_OK);
+  parallel_for(L->n, [&](int i) {
+    try {
+      std::memset(&packed[i].g, 0, sizeof(LigDev));
+      pack_ligand(L->host[i], tab, packed[i]);
+    } catch (const std::bad_alloc&) {
+      pack_rc[i] = DOCK_E_OOM;
+    } catch (...) {
+      pack_rc[i] = DOCK_E_ARG;
+    }
+  });
+  for (int i = 0; i < L->n; ++i)
+    if (pack_rc[i] != DOCK_OK) {
+      delete L;
+      return fail(pack_rc[i], "ligand " + std::to_string(i) + ": packing failed");
+    }
   std::vector<float4> atoms;
   std::vector<FragDev> frags;
   std::vector<TorsDev> tors;
   std::vector<PairRec> pairs;
-  TypePair tab[kTypes * kTypes];
-  type_pair_table(DOCK_PRESET_TRIDS, tab);
   L->h_ligs.resize(L->n);
   for (int i = 0; i < L->n; ++i) {
-    const LigandHost& H = L->host[i];
+    PackedLigand& P = packed[i];
     LigDev& g = L->h_ligs[i];
-    std::memset(&g, 0, sizeof g);
-    g.n_atoms = H.n_atoms;
-    g.n_tors = H.n_tors;
-    g.n_frags = H.n_frags;
-    g.n_pairs = int(H.pair_i.size());
-    g.atom_off = int(atoms.size());
-    g.pair_off = int(pairs.size());
-    g.frag_off = int(frags.size());
-    g.tors_off = int(tors.size());
-    g.pocket = H.pocket;
-    g.n_dof = 6 + H.n_tors;
-    g.fk_rounds = bit_length(H.height);
-    for (int c = 0; c < 3; ++c) {
-      g.c0[c] = float(H.c0[c]);
-      g.box_min[c] = H.box_min[c];
-      g.box_max[c] = H.box_max[c];
-    }
-    // coordinates relative to the root centroid c0 (FP64 difference, rounded
-    // once): the rotation then acts on vectors of ligand size, not on
-    // absolute positions, which keeps FP32 forward kinematics accurate
-    for (int na = 0; na < H.n_atoms; ++na) {
-      const int a = H.dfs_atom[na];
-      const int bits = int(H.type[a]) | (H.frag_new[H.atom_frag[a]] << 8) | (a << 16);
-      float4 v = make_float4(float(double(H.x0[3 * a]) - H.c0[0]), float(double(H.x0[3 * a + 1]) - H.c0[1]),
-                             float(double(H.x0[3 * a + 2]) - H.c0[2]), 0.f);
-      std::memcpy(&v.w, &bits, 4);
-      atoms.push_back(v);
-    }
-    std::vector<int> frag_tors(H.n_frags, -1);
-    for (int k = 0; k < H.n_tors; ++k) frag_tors[H.tors_frag[k]] = k;
-    for (int nf = 0; nf < H.n_frags; ++nf) {
-      const int f = H.dfs_frag[nf];
-      FragDev fd{};
-      if (H.frag_parent[f] < 0) {
-        fd.parent = -1;
-        fd.dof = -1;
-      } else {
-        const int k = frag_tors[f];
-        const int a = H.tors_a[k], b = H.tors_b[k];
-        double u[3], n2 = 0;
-        for (int c = 0; c < 3; ++c) {
-          u[c] = double(H.x0[3 * b + c]) - double(H.x0[3 * a + c]);
-          n2 += u[c] * u[c];
-        }
-        const double inv = 1.0 / std::sqrt(n2);
-        for (int c = 0; c < 3; ++c) {
-          fd.u[c] = float(u[c] * inv);
-          fd.xb[c] = float(double(H.x0[3 * b + c]) - H.c0[c]);
-        }
-        fd.parent = H.frag_new[H.frag_parent[f]];
-        fd.dof = 6 + k;
-      }
-      frags.push_back(fd);
-    }
-    // torsion k moves the DFS subtree of its child fragment: a contiguous range
-    std::vector<int> first(H.n_frags, 0), last(H.n_frags, 0);  // atom range per new frag id
-    {
-      std::vector<int> start(H.n_frags, -1), stop(H.n_frags, -1);
-      for (int na = 0; na < H.n_atoms; ++na) {
-        const int nf = H.frag_new[H.atom_frag[H.dfs_atom[na]]];
-        if (start[nf] < 0) start[nf] = na;
-        stop[nf] = na + 1;
-      }
-      // subtree end = max stop over the DFS subtree; in pre-order the subtree
-      // of nf is nf .. nf + size - 1
-      std::vector<int> size(H.n_frags, 1);
-      for (int nf = H.n_frags - 1; nf >= 1; --nf) {
-        const int par = frags[g.frag_off + nf].parent;
-        size[par] += size[nf];
-      }
-      for (int nf = 0; nf < H.n_frags; ++nf) {
-        first[nf] = start[nf];
-        last[nf] = stop[nf + size[nf] - 1];
-      }
-    }
-    for (int k = 0; k < H.n_tors; ++k) {
-      const int nf = H.frag_new[H.tors_frag[k]];
-      TorsDev t{};
-      t.sub_begin = first[nf];
-      t.sub_end = last[nf];
-      t.a = H.atom_new[H.tors_a[k]];
-      t.b = H.atom_new[H.tors_b[k]];
-      tors.push_back(t);
-    }
-    // device pair records: with one atom per lane, passes of one group's
-    // width whose forces are gathered per atom (no LDS atomics); with two
-    // atoms per lane, the caller's order, strided over the lanes
-    std::vector<int> pi_new(H.pair_i.size()), pj_new(H.pair_j.size());
-    for (size_t p = 0; p < H.pair_i.size(); ++p) {
-      pi_new[p] = H.atom_new[H.pair_i[p]];
-      pj_new[p] = H.atom_new[H.pair_j[p]];
-    }
-    auto record = [&](int i0, int j0) {
-      PairRec pr{};
-      if (i0 < 0) {
-        pr.w = kPairEmpty;
-        pr.rsum = kEmptyRsum;
-        return pr;
-      }
-      const int ti = H.type[H.dfs_atom[i0]], tj = H.type[H.dfs_atom[j0]];
-      const TypePair& tp = tab[ti * kTypes + tj];
-      pr.w = uint32_t(i0) | (uint32_t(j0) << 8) | (uint32_t(ti) << 16) | (uint32_t(tj) << 20) |
-             (tp.flags << 24);
-      pr.rsum = tp.rsum;
-      return pr;
-    };
-    auto bits = [](float f) {
-      uint32_t u;
-      std::memcpy(&u, &f, 4);
-      return u;
-    };
-    // one pair layout for a lane configuration, appended to `pairs`
-    auto emit_layout = [&](const LaneCfg& lc) {
-      PairLayout lay{};
-      lay.pair_off = int(pairs.size());
-      PassPlan plan;
-      if (!pi_new.empty()) plan = schedule_passes(H.n_atoms, pi_new, pj_new, lc.lpp, lc.apl);
-      // the pass layout stages 2 entries per slot and apl * cap pull bytes
-      // per lane and pass; with two atoms per lane above 64 atoms it is kept
-      // only where it fits the LDS budget
-      const size_t pull_bytes = size_t(plan.n_pass) * lc.lpp * lc.apl * plan.cap;
-      const size_t pass_entries = plan.slot_i.size() * 2 + pull_bytes / sizeof(PairRec) + 1;
-      if (plan.n_pass > 0 &&
-          (H.n_atoms <= 64 || pass_entries * sizeof(PairRec) <= kPassStageBytes)) {
-        lay.n_pass = plan.n_pass;
-        lay.pass_w = lc.lpp;
-        lay.pass_apl = lc.apl;
-        lay.pull_cap = plan.cap;
-        // 16-byte slot records (pair word, radius sum, d_clash^2 as the
-        // device squares it, log2 d_clash), then the pull bytes
-        for (size_t s = 0; s < plan.slot_i.size(); ++s) {
-          const int i0 = plan.slot_i[s], j0 = plan.slot_j[s];
-          pairs.push_back(record(i0, j0));
-          PairRec cl{};
-          if (i0 >= 0) {
-            const TypePair& tp = tab[H.type[H.dfs_atom[i0]] * kTypes + H.type[H.dfs_atom[j0]]];
-            // negated for a donor/acceptor pair: the kernel tests
-            // |d_clash^2| for the clash term and the sign for the
-            // hydrogen-bond term
-            cl.w = bits((tp.flags & 1u) ? -tp.dclash2 : tp.dclash2);
-            cl.rsum = float(std::log2(double(tp.dclash)));
-          }
-          pairs.push_back(cl);
-        }
-        // pull bytes per (pass, lane): the lane's atoms one after the other,
-        // the first `cap` bytes of each atom's pull list
-        std::vector<uint8_t> pb(pull_bytes);
-        const int per_lane = lc.apl * plan.cap;
-        for (int ps = 0; ps < plan.n_pass; ++ps)
-          for (int ln = 0; ln < lc.lpp; ++ln)
-            for (int sa = 0; sa < lc.apl; ++sa) {
-              const uint64_t w = plan.pulls[size_t(ps) * plan.n_pull + lc.apl * ln + sa];
-              for (int b = 0; b < plan.cap; ++b)
-                pb[(size_t(ps) * lc.lpp + ln) * per_lane + sa * plan.cap + b] = uint8_t(w >> (8 * b));
-            }
-        for (size_t o = 0; o < pb.size(); o += sizeof(PairRec)) {
-          PairRec pw;
-          std::memcpy(&pw, pb.data() + o, sizeof(PairRec));
-          pairs.push_back(pw);
-        }
-        // padding: the kernel reads each 4-byte pull word with its successor
-        pairs.push_back(PairRec{});
-        lay.n_prec = int(plan.slot_i.size());
-      } else {
-        for (size_t p = 0; p < pi_new.size(); ++p) pairs.push_back(record(pi_new[p], pj_new[p]));
-        lay.n_prec = int(pi_new.size());
-      }
-      lay.n_stage = int(pairs.size()) - lay.pair_off;
-      return lay;
-    };
-    const LaneCfg lc = lane_cfg(g, 0), la = lane_cfg(g, 0, true);
-    const PairLayout prim = emit_layout(lc);
-    g.pair_off = prim.pair_off;
-    g.n_prec = prim.n_prec;
-    g.n_pass = prim.n_pass;
-    g.pass_w = prim.pass_w;
-    g.pull_cap = prim.pull_cap;
-    g.pass_apl = prim.pass_apl;
-    g.alt = (la.lpp == lc.lpp && la.apl == lc.apl) ? prim : emit_layout(la);
-    g.n_stage = prim.n_stage;
+    g = P.g;
+    g.atom_off += int(atoms.size());
+    g.frag_off += int(frags.size());
+    g.tors_off += int(tors.size());
+    g.pair_off += int(pairs.size());
+    g.alt.pair_off += int(pairs.size());
+    atoms.insert(atoms.end(), P.atoms.begin(), P.atoms.end());
+    frags.insert(frags.end(), P.frags.begin(), P.frags.end());
+    tors.insert(tors.end(), P.tors.begin(), P.tors.end());
+    pairs.insert(pairs.end(), P.pairs.begin(), P.pairs.end());
+    P = PackedLigand{};
+    const LigandHost& H = L->host[i];
     L->max_atoms = std::max(L->max_atoms, H.n_atoms);
     L->max_tors = std::max(L->max_tors, H.n_tors);
     L->max_pairs = std::max({L->max_pairs, g.n_stage, g.alt.n_stage});

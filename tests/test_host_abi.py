@@ -153,3 +153,33 @@ def test_autotune_cache_saved_and_restored(tmp_path):
     assert {(e["lanes"], e["atoms_per_lane"], e["chosen_lanes"], e["block"]) for e in before} == \
         {(32, 2, 32, 128), (16, 1, 32, 256)}
     D.dock_autotune_clear()
+
+
+def test_parallel_preparation_matches_one_thread(monkeypatch):
+    # ligand preparation and packing run on OMP_NUM_THREADS host threads;
+    # the result must not depend on how many
+    L = synth.make_ligands(700, lambda r: int(r.integers(5, 71)), lambda r: int(r.integers(0, 16)), seed=8)
+    got = []
+    for nt in ("1", "6"):
+        monkeypatch.setenv("OMP_NUM_THREADS", nt)
+        H = D.dock_load_ligands(L.atom_off, L.element, L.n_h, L.xyz, L.bond_off, L.bonds, L.rotatable,
+                                host_only=True)
+        got.append([D.dock_ligand_topology(H, i) for i in range(L.n_ligands)])
+    for a, b in zip(*got):
+        assert a.keys() == b.keys()
+        for k in a:
+            assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+
+
+def test_parallel_preparation_reports_the_first_failing_ligand(monkeypatch):
+    # ligands 3 and 5 (of 8) are disconnected: the error names ligand 3
+    monkeypatch.setenv("OMP_NUM_THREADS", "4")
+    parts = [synth.make_ligand(6, 1, np.random.default_rng(k)) for k in range(8)]
+    for k in (3, 5):
+        parts[k]["bonds"] = parts[k]["bonds"][:-1]
+        parts[k]["rotatable"] = parts[k]["rotatable"][:-1]
+    L = synth.pack_ligands(parts)
+    with pytest.raises(D.DockError) as ei:
+        D.dock_load_ligands(L.atom_off, L.element, L.n_h, L.xyz, L.bond_off, L.bonds, L.rotatable,
+                            host_only=True)
+    assert ei.value.code == -2 and "ligand 3:" in str(ei.value)
