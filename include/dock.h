@@ -164,6 +164,11 @@ typedef struct {
                                   (such a handle serves dock_ligand_* queries) */
 } dock_ligand_desc;
 
+/* Prepares the ligands on the host, one ligand per task on OMP_NUM_THREADS
+ * threads (default: the hardware's, at most 64; the result does not depend
+ * on the count), then uploads the packed arrays with synchronous copies.
+ * On a failing ligand returns its code with the lowest failing index named
+ * in dock_last_error(). */
 int dock_load_ligands(const dock_ligand_desc* desc, void* stream, dock_ligands_t* out);
 
 typedef struct {
