@@ -1234,13 +1234,14 @@ struct dock_run_s {
   size_t events_used = 0;
   bool recording = false;
   // batched form: the buckets run in groups, one per occupancy class (blocks
-  // per CU), highest first.  The buckets of a group run concurrently: the
-  // first on the caller's stream, the k-th on side[k - 1], forked from and
-  // joined back into the caller's stream, so a bucket too small to fill the
-  // chip and the tail of a large one overlap.  A group starts when the one
-  // before it has ended: blocks of kernels of different occupancy classes
-  // sharing a CU lower the waves it holds.  The side streams belong to the
-  // device's process-wide pool (side_streams).
+  // per CU) of the buckets that fill the chip, highest first; buckets too
+  // small to fill it join the first group.  The buckets of a group run
+  // concurrently: the first on the caller's stream, the k-th on side[k - 1],
+  // forked from and joined back into the caller's stream, so a bucket too
+  // small to fill the chip and the tail of a large one overlap.  A group
+  // starts when the one before it has ended: blocks of kernels of different
+  // occupancy classes sharing a CU lower the waves it holds.  The side
+  // streams belong to the device's process-wide pool (side_streams).
   std::vector<std::vector<int>> occ_groups;
   std::vector<hipStream_t> side;
   std::vector<std::vector<hipEvent_t>> join;  // [group][side stream]
@@ -1690,14 +1691,19 @@ static int create_run(const dock_pocket_t* pockets, int32_t n_pockets, dock_liga
       B.grid = std::min(B.n_items, per_cu * n_cu);
       B.per_cu = per_cu;
     }
-    // launch groups: one per occupancy class, highest first
+    // launch groups: one per occupancy class of the buckets whose grid fills
+    // the chip, highest first; a bucket too small to fill the chip joins the
+    // first group (it gains from overlapping and displaces little)
+    auto fills = [&](const Bucket& B) { return B.grid >= B.per_cu * n_cu; };
+    int top = 0;
+    for (const Bucket& B : r->buckets)
+      if (fills(B)) top = std::max(top, B.per_cu);
+    auto rank = [&](int b) { return fills(r->buckets[b]) ? r->buckets[b].per_cu : top; };
     std::vector<int> order(r->buckets.size());
     for (size_t b = 0; b < order.size(); ++b) order[b] = int(b);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return r->buckets[x].per_cu > r->buckets[y].per_cu; });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return rank(x) > rank(y); });
     for (const int b : order) {
-      if (r->occ_groups.empty() || r->buckets[r->occ_groups.back()[0]].per_cu != r->buckets[b].per_cu)
-        r->occ_groups.emplace_back();
+      if (r->occ_groups.empty() || rank(r->occ_groups.back()[0]) != rank(b)) r->occ_groups.emplace_back();
       r->occ_groups.back().push_back(b);
     }
   }
