@@ -300,7 +300,8 @@ void dock_sample_params_default(dock_sample_params* p);
 /* Creates a run, draws the initial poses, scores them and advances every
  * trajectory by p->n_steps MC steps.  The run owns its state buffers.
  * In the batched form the lane buckets run in groups, one per occupancy
- * class (blocks per CU), highest first, each group after the previous one;
+ * class (blocks per CU) of the buckets whose grid fills the device, highest
+ * first, each group after the previous one (smaller buckets join the first);
  * within a group the first bucket runs on `stream` and the others on side
  * streams forked from `stream` and joined back into it.  The library keeps
  * a pool of side streams per device for the life of the process, shared by
